@@ -1,0 +1,178 @@
+"""Throughput benchmark of the TENO7X operator on MI355X: 2D Euler, 4096 x 4096, FP64, SSP-RK3.
+
+One step = one SSP-RK3 step of the whole hot path: CFL dt from the state on the device, three
+evaluations of the semi-discrete operator (x- and y-sweeps: Roe-averaged characteristic
+projection, GLF splitting, TENO5 flags, neighbour-vector selection (Table 3), Table 2
+reconstruction, conservative difference) and the three stage updates with the wave-speed
+maxima of each produced state. Input: the seeded four-quadrant Riemann state with a vortex,
+resident in HBM before the timed region. The step is captured once in a HIP graph and replayed.
+
+value = cells * 3 * steps / wall time  (cell-updates per second, one GPU), reported in Gcell-updates/s.
+
+Prints one JSON line (see the repository's design notes for the roofline and baseline fields).
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X published peaks
+PEAK_HBM = 8.0e12           # B/s
+PEAK_FP64_VALU = 78.6e12    # FLOP/s (vector FP64)
+
+# Algorithmic work per cell of one sweep kernel, 2D Euler FP64 (derivation in the design notes):
+# per face 1156 flops (Roe average 23, L 15, R 6, projection 368, GLF split 160, smoothness and
+# cut-off of 2 sides x 4 fields 456, reconstruction 108, back-projection 20), per cell 16 (primitive
+# variables, H, sqrt(rho), physical flux) + 8 (conservative difference).
+FLOPS_YSWEEP = 1156 + 16 + 8
+# the x-sweep also adds the y-part (4), applies the RK stage (16) and the wave speeds of the
+# produced state (25)
+FLOPS_XSTAGE = 1156 + 16 + 8 + 4 + 16 + 25
+# algorithmic HBM bytes per cell-update of a fused stage: read U^(k) and write U^(k+1) (64 B),
+# plus U^n at stages 2 and 3 (32 B): mean 85.3 B
+BYTES_PER_CELL_UPDATE = (64 + 96 + 96) / 3.0
+
+METRIC = "2D Euler RHS Gcell-updates/s, %HBM peak; batched vs plain; adjoint/fwd cost"
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for name in ("teno_device.hpp",):
+        with open(os.path.join(ROOT, "paper_1808_00037_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the x-sweep stage kernel from the committed rocprofv3 --pmc
+    summary, if it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "sweep_x_stage_euler2d_4096_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("kernel_source_sha") != kernel_source_hash():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def cpu_baseline(problem, budget_s=12.0):
+    """The oracle (plain C, one thread) on a bounded sample of the same workload: one operator
+    evaluation on a horizontal strip of the 4096^2 state (periodic), the strip height chosen so
+    that the sample takes about budget_s seconds."""
+    import numpy as np
+    from oracle import oracle as O
+
+    def timed(rows):
+        U = np.ascontiguousarray(problem.U0[:, :rows, :])
+        cfg = O.Config(O.EULER2D, problem.nx, rows, 0.0, 1.0, 0.0, rows / problem.ny)
+        t0 = time.perf_counter()
+        O.rhs(cfg, U)
+        return time.perf_counter() - t0
+
+    t_probe = timed(16)
+    rate = problem.nx * 16 / t_probe
+    rows = int(min(problem.ny, max(16, budget_s * rate / problem.nx)))
+    t = timed(rows)
+    cells = problem.nx * rows
+    return {"value": cells / t / 1e9, "unit": "Gcell-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"one operator evaluation (FP64, single thread) on a {problem.nx}x{rows} periodic strip "
+                      f"of the {problem.nx}x{problem.ny} state, {t:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--n", type=int, default=4096)
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-extras", action="store_true", help="skip the batched and adjoint side runs")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+    from paper_1808_00037_amd import teno as T
+    from paper_1808_00037_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    n = args.n
+    log(f"building the 2D Euler {n}x{n} state")
+    pr = W.euler2d(args.seed, n=n, nsteps=args.steps)
+    U = torch.from_numpy(pr.U0).cuda()
+    sv = T.Solver.for_problem(pr)
+    cells = n * n
+
+    log("warmup")
+    sv.run(U, args.warmup, graph=True)
+    torch.cuda.synchronize()
+    sv.poll()
+
+    log(f"timed region: {args.steps} steps")
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    sv.run(U, args.steps, graph=True)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    sv.poll()
+    ms_per_step = ms / args.steps
+    value = cells * 3 * args.steps / (ms / 1e3) / 1e9
+    log(f"{ms_per_step:.3f} ms/step, {value:.2f} Gcell-updates/s (wall {wall:.2f} s)")
+
+    # per-kernel durations, HIP events on the launch stream, eager launches of the same steps
+    ksteps = min(args.steps, 10)
+    sv.set_timing(True)
+    sv.run(U, ksteps, graph=False)
+    kt = sv.read_timing()
+    sv.set_timing(False)
+    sv.poll()
+    x_ms = kt["x"][0] / max(kt["x"][1], 1)
+    y_ms = kt["y"][0] / max(kt["y"][1], 1)
+    log(f"x-sweep+stage {x_ms:.3f} ms, y-sweep {y_ms:.3f} ms per launch")
+    flops_x = FLOPS_XSTAGE * cells
+    achieved = flops_x / (x_ms / 1e3)
+    roofline = {"bound": "alu", "kernel": "sweep_kernel<double,EULER2D,x,stage>", "achieved": achieved / 1e12,
+                "peak": PEAK_FP64_VALU / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU,
+                "traffic": measured_traffic(), "avg_launch_ms": x_ms,
+                "flops_per_cell": FLOPS_XSTAGE}
+    hbm_frac = value * 1e9 * BYTES_PER_CELL_UPDATE / PEAK_HBM
+
+    out = {"metric": METRIC, "value": value, "unit": "Gcell-updates/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"euler2d_{n}x{n}_fp64_ssprk3", "nx": n, "ny": n, "cfl": pr.cfl,
+                      "seed": args.seed, "bc": "periodic", "scheme": "TENO7X", "eps": "dx^3", "C_T": 1e-5},
+           "roofline": roofline,
+           "hbm": {"algorithmic_bytes_per_cell_update": BYTES_PER_CELL_UPDATE,
+                   "achieved_GBps": value * BYTES_PER_CELL_UPDATE, "peak_GBps": PEAK_HBM / 1e9, "frac": hbm_frac},
+           "kernels_ms": {"x_sweep_stage": x_ms, "y_sweep": y_ms}}
+
+    del sv, U
+    torch.cuda.empty_cache()
+    if not args.no_cpu:
+        log("oracle CPU baseline")
+        out["cpu_baseline"] = cpu_baseline(pr)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,197 @@
+/*
+ * teno.h -- C ABI of the MI355X (gfx950) library for the TENO7X semi-discrete operator.
+ *
+ * Method: F. Zhang, J. Liu, H. Zhang, C. Xu, "An extending strategy based on TENO framework for
+ * hyperbolic conservation laws" (arXiv:1808.00037). Equations are named by their labels in the
+ * paper's source (eq:app, eq:smooth_expl, eq:TENO1, eq:norm, eq:seclect, eq:vec; Tables 1-3).
+ *
+ * Conventions shared by every entry point
+ *  - Pointers named U, dUdt, lam, grad, F*, masks*, flags*, *_dev are DEVICE pointers owned by the
+ *    caller. The library never frees caller memory.
+ *  - States are structure-of-arrays [nvar][ny][nx], contiguous, element type given by the grid's
+ *    dtype (double for TENO_F64, float for TENO_F32). nvar = 1 (scalar), 3 (1D Euler),
+ *    4 (2D Euler: rho, rho u, rho v, E). ny = 1 for one-dimensional systems.
+ *  - Faces: face f of a line is the left face of cell f (f = 0..len). x-face arrays are
+ *    [..][ny][nx+1], y-face arrays [..][ny+1][nx]. Face-word arrays (masks, flags) hold the x-faces
+ *    first, then (2D) the y-faces: teno_nfaces() words in total.
+ *  - Mask word of a face: bits 8s..8s+3 = stencil code of the left-biased ('+') reconstruction of
+ *    characteristic field s, bits 8s+4..8s+7 = code of the right-biased ('-') one. TENO7X codes are
+ *    the candidate index m of Table 2 (0..12); TENO5 codes are (delta0<<2)|(delta1<<1)|delta2.
+ *  - Flag word of a face: bits 6s+k = cut-off flag delta_k of the '+' side, bits 6s+3+k of the
+ *    '-' side (eq:seclect), k = 0..2, field s.
+ *  - All work is enqueued on the context's HIP stream and returns immediately. Argument errors are
+ *    returned synchronously; device-side failures (non-finite or non-physical states, impossible
+ *    selection patterns) set a sticky error word that teno_poll() reads (and clears).
+ *  - A context is not thread-safe; use one context per host thread or stream.
+ */
+#ifndef TENO_H
+#define TENO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TENO_OK = 0,
+    TENO_E_ARG = -1,          /* invalid argument (null pointer, size, enum value) */
+    TENO_E_UNSUPPORTED = -2,  /* valid request the library does not implement */
+    TENO_E_HIP = -3,          /* a HIP runtime call failed */
+    TENO_E_NONFINITE = -4,    /* a NaN/Inf reached a smoothness measure or state */
+    TENO_E_NONPHYSICAL = -5,  /* density, pressure or Roe sound speed squared <= 0 */
+    TENO_E_STATE = -6         /* call not valid in the context's current state */
+} teno_status;
+
+typedef enum { TENO_ADV1D = 0, TENO_EULER1D = 1, TENO_EULER2D = 2, TENO_BURGERS1D = 3 } teno_system;
+typedef enum { TENO_SCHEME_TENO7X = 0, TENO_SCHEME_TENO5 = 1 } teno_scheme;
+typedef enum { TENO_BC_PERIODIC = 0, TENO_BC_OUTFLOW = 1 } teno_bc;
+typedef enum { TENO_F64 = 0, TENO_F32 = 1 } teno_dtype;
+
+/* Uniform grid of cell centres x_i = x0 + (i + 1/2) dx, dx = (x1 - x0)/nx (point values, eq:flux). */
+typedef struct {
+    int32_t sys;      /* teno_system */
+    int32_t nx, ny;   /* cells; ny = 1 for 1D systems; 1 <= nx, ny <= 2^20, nvar*nx*ny < 2^31 */
+    int32_t bc_x, bc_y; /* teno_bc; outflow = zero-gradient copy of the boundary cell */
+    int32_t dtype;    /* teno_dtype */
+    double x0, x1, y0, y1;
+} teno_grid;
+
+typedef struct {
+    int32_t scheme;     /* teno_scheme; TENO7X is the paper's presented method */
+    int32_t alpha_mode; /* 0: Lax-Friedrichs constant per characteristic field, max_j |lambda_s(U_j)|;
+                           1: one constant max_j(|u_n| + c) for all fields */
+    int32_t eps_mode;   /* 0: eps = dx^3 per direction for TENO7X (section "The parameter epsilon"),
+                           1e-40 for TENO5 (eq:TENO1); 1: the constant `eps` below */
+    int32_t reserved;
+    double gamma;       /* ratio of specific heats (1.4) */
+    double ct;          /* cut-off C_T of eq:seclect (1e-5) */
+    double eps;         /* used when eps_mode = 1 */
+    double cfl;         /* CFL number of the time-step rule */
+    double adv_speed;   /* a of u_t + a u_x = 0 (TENO_ADV1D) */
+} teno_opts;
+
+typedef struct teno_ctx teno_ctx;
+
+/* Fill *o with the paper's parameters: TENO7X, per-field alpha, eps = dx^3, gamma = 1.4,
+ * C_T = 1e-5, CFL 0.5, a = 1. */
+void teno_default_opts(teno_opts *o);
+
+/* Human-readable name of a status code (static string). */
+const char *teno_status_str(teno_status s);
+
+/* Create a context for one problem on the current HIP device; `stream` is a hipStream_t (NULL =
+ * the null stream). Allocates the context's own device scratch: three state-sized buffers for the
+ * RK3 stages and a small control block. Errors: TENO_E_ARG for an invalid grid/opts,
+ * TENO_E_HIP if an allocation fails. */
+teno_status teno_create(const teno_grid *grid, const teno_opts *opts, void *stream, teno_ctx **out);
+
+/* Release the context and its scratch (never caller memory). Synchronises its stream. */
+teno_status teno_destroy(teno_ctx *ctx);
+
+/* Elements of one state (nvar*nx*ny) and face words (x-faces + y-faces). */
+size_t teno_state_elems(const teno_ctx *ctx);
+size_t teno_nfaces(const teno_ctx *ctx);
+
+/* Replace the context's stream (hipStream_t). */
+teno_status teno_set_stream(teno_ctx *ctx, void *stream);
+
+/* The semi-discrete operator dU/dt = L(U) (eq:app): per face, the five-point TENO smoothness
+ * measure and cut-off of every characteristic field and both split sides (eq:smooth_expl,
+ * eq:tau5, eq:TENO1, eq:norm, eq:seclect), the neighbour vector of eq:vec mapped by Table 3
+ * (TENO7X) to a Table 2 reconstruction, Roe-averaged characteristic projection with global
+ * Lax-Friedrichs splitting (Remark 3), and the conservative difference, in x then (2D) y.
+ * The Lax-Friedrichs constants come from U itself. U and dUdt must not overlap.
+ * masks_out (nullable): teno_nfaces() mask words. */
+teno_status teno_rhs(teno_ctx *ctx, const void *U, void *dUdt, uint32_t *masks_out);
+
+/* Parity/debug form of teno_rhs: the numerical face fluxes Fx [nvar][ny][nx+1] and (2D)
+ * Fy [nvar][ny+1][nx], mask and flag words (each nullable except Fx), and the eight Lax-Friedrichs
+ * constants used (alpha_dev, nullable: [0..3] x-fields, [4..7] y-fields, double). */
+teno_status teno_face_fluxes(teno_ctx *ctx, const void *U, void *Fx, void *Fy, uint32_t *masks,
+                             uint32_t *flags, double *alpha_dev);
+
+/* The operator with the selection (masks, teno_nfaces() words) and the eight Lax-Friedrichs
+ * constants (alpha_dev, double) held fixed instead of computed from U. */
+teno_status teno_rhs_frozen(teno_ctx *ctx, const void *U, const uint32_t *masks, const double *alpha_dev,
+                            void *dUdt);
+
+/* One SSP-RK3 step in Shu-Osher form (the paper cites Gottlieb, Shu & Tadmor 2001 and omits the
+ * formula): U1 = U + dt L(U); U2 = 3/4 U + 1/4 (U1 + dt L(U1)); U <- 1/3 U + 2/3 (U2 + dt L(U2)).
+ * dt_fixed > 0 sets dt; otherwise dt = cfl / max_j((|u|+c)/dx [+ (|v|+c)/dy]) from U on the
+ * device (no host synchronisation). U is updated in place. */
+teno_status teno_step(teno_ctx *ctx, void *U, double dt_fixed);
+
+/* nsteps calls of teno_step. use_graph = 1 captures one step into a HIP graph on first use and
+ * replays it (identical results; fewer launches). */
+teno_status teno_run(teno_ctx *ctx, void *U, int32_t nsteps, double dt_fixed, int32_t use_graph);
+
+/* Synchronise the stream and return (then clear) the sticky device error status. */
+teno_status teno_poll(teno_ctx *ctx);
+
+/* dt of the most recent step (synchronises). */
+teno_status teno_last_dt(teno_ctx *ctx, double *dt_host);
+
+/* ------------------------------------------------------------------------------ measurement ----
+ * Per-kernel timing with HIP events recorded on the context's stream around every sweep launch
+ * (eager launches only; graph replays are not instrumented). kind 0 = x-sweep (with the RK stage
+ * update when stepping), kind 1 = y-sweep. */
+teno_status teno_set_timing(teno_ctx *ctx, int32_t enable);
+/* Synchronise, then return for each kind the summed duration in ms and the launch count since
+ * timing was enabled (arrays of 2). */
+teno_status teno_read_timing(teno_ctx *ctx, double *ms, int32_t *count);
+
+/* ---------------------------------------------------------------- frozen-selection adjoint ----
+ * These entry points differentiate the operator and the RK3 trajectory with every stencil
+ * selection, every Lax-Friedrichs constant and every dt held at the values of a recorded forward
+ * run (the selection is piecewise constant in U, so this is the derivative almost everywhere).
+ * Only TENO_F64 contexts support them. */
+
+/* Vector-Jacobian product of the frozen operator at U: grad = (dL/dU)^T lam. Overwrites grad. */
+teno_status teno_rhs_vjp(teno_ctx *ctx, const void *U, const uint32_t *masks, const double *alpha_dev,
+                         const void *lam, void *grad);
+
+/* Forward run of nsteps steps that records what the adjoint needs: ckpt_dev holds
+ * (nsteps/ckpt_every + 1) states (the state before steps 0, ckpt_every, 2*ckpt_every, ...),
+ * masks_dev (nullable) nsteps*3*teno_nfaces() mask words, alpha_dt_dev nsteps*(3*8+1) doubles
+ * (per step: the three stages' eight constants, then dt). U is advanced in place. */
+teno_status teno_run_record(teno_ctx *ctx, void *U, int32_t nsteps, double dt_fixed, int32_t ckpt_every,
+                            void *ckpt_dev, uint32_t *masks_dev, double *alpha_dt_dev);
+
+/* The frozen forward map from the state U over nsteps recorded steps (same masks/alpha/dt). */
+teno_status teno_run_replay(teno_ctx *ctx, void *U, int32_t nsteps, const uint32_t *masks_dev,
+                            const double *alpha_dt_dev);
+
+/* Reverse sweep: given lam = dJ/dU(T) in lam_io, overwrite it with dJ/dU(0). Recomputes each
+ * checkpoint segment forward (frozen) and applies the adjoint of every RK stage in reverse.
+ * Needs masks_dev (recorded). Scratch: 3*ckpt_every+1 states allocated on first use. */
+teno_status teno_run_vjp(teno_ctx *ctx, const void *ckpt_dev, const uint32_t *masks_dev,
+                         const double *alpha_dt_dev, int32_t nsteps, int32_t ckpt_every, void *lam_io);
+
+/* -------------------------------------------------------------------------------- batching ----
+ * Many independent problems (1D and 2D Euler mixed, uneven sizes, same dtype and options)
+ * advanced together. The batch owns a packed state buffer; instance k's state lives at element
+ * offset teno_batch_offset(b, k) with the usual [nvar][ny][nx] layout. */
+typedef struct teno_batch teno_batch;
+
+teno_status teno_batch_create(const teno_grid *grids, int32_t n, const teno_opts *opts, void *stream,
+                              teno_batch **out);
+teno_status teno_batch_destroy(teno_batch *b);
+size_t teno_batch_total_elems(const teno_batch *b);
+size_t teno_batch_offset(const teno_batch *b, int32_t k);
+
+/* Advance every instance by nsteps SSP-RK3 steps (each instance with its own CFL dt).
+ * mode 0: all instances per kernel in persistent work-queue launches, the step captured once in
+ * a HIP graph and replayed; mode 1: one launch per instance per kernel (reference form).
+ * U_dev: the packed state of teno_batch_total_elems() elements. Both modes give bitwise equal
+ * results. */
+teno_status teno_batch_run(teno_batch *b, void *U_dev, int32_t nsteps, int32_t mode);
+
+/* Synchronise and return (then clear) the batch's sticky device error status. */
+teno_status teno_batch_poll(teno_batch *b);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TENO_H */

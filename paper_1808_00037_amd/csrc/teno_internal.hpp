@@ -1,0 +1,36 @@
+// teno_internal.hpp -- host-side context layout shared by the library's translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "teno.h"
+#include "teno_device.hpp"
+
+#include <utility>
+#include <vector>
+
+struct teno_ctx {
+    teno_grid grid;
+    teno_opts opts;
+    hipStream_t stream = nullptr;
+    int nv = 1;
+    double dx = 1, dy = 1, eps_x = 0, eps_y = 0;
+    size_t ncell = 0, nelem = 0, nfx = 0, nfy = 0, esize = 8;
+    teno::Ctrl *ctrl_d = nullptr;
+    void *S1 = nullptr, *S2 = nullptr, *dUy = nullptr;
+    // adjoint scratch (stage states of one checkpoint segment, adjoint work arrays)
+    void *adj_scratch = nullptr;
+    size_t adj_scratch_bytes = 0;
+    // captured step graph
+    hipStream_t cap_stream = nullptr;   // private stream used only to capture graphs
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    void *graph_U = nullptr;
+    double graph_dt = 0.0;
+    // kernel timing (eager launches only)
+    bool timing = false;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> events;
+    size_t events_used = 0;
+};
+
+bool teno_validate(const teno_grid *g, const teno_opts *o);
+void teno_fill_derived(teno_ctx *c);

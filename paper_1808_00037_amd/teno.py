@@ -1,0 +1,318 @@
+"""Python binding of the gfx950 TENO7X library (include/teno.h) through ctypes.
+
+Argument marshalling only: every step of the operator, the time stepper, the adjoint and the
+batched runs executes in the HIP kernels of libteno.so. torch provides device memory and the
+current stream. There is no CPU fallback: without the built library on a GPU machine every call fails.
+
+States are torch tensors on the GPU, shape [nvar, ny, nx], contiguous, float64 (or float32 for
+single-precision contexts); conserved variables (rho, rho u, [rho v], E).
+"""
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libteno.so")
+
+ADV1D, EULER1D, EULER2D, BURGERS1D = 0, 1, 2, 3
+TENO7X, TENO5 = 0, 1
+PERIODIC, OUTFLOW = 0, 1
+F64, F32 = 0, 1
+NVAR = {ADV1D: 1, EULER1D: 3, EULER2D: 4, BURGERS1D: 1}
+
+STATUS = {0: "ok", -1: "invalid argument", -2: "unsupported", -3: "HIP runtime error",
+          -4: "non-finite value", -5: "non-physical state", -6: "invalid context state"}
+
+
+class TenoError(RuntimeError):
+    def __init__(self, code, where):
+        super().__init__(f"{where}: {STATUS.get(code, code)} ({code})")
+        self.code = code
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("sys", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("bc_x", ctypes.c_int32), ("bc_y", ctypes.c_int32), ("dtype", ctypes.c_int32),
+                ("x0", ctypes.c_double), ("x1", ctypes.c_double), ("y0", ctypes.c_double),
+                ("y1", ctypes.c_double)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("scheme", ctypes.c_int32), ("alpha_mode", ctypes.c_int32), ("eps_mode", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("gamma", ctypes.c_double), ("ct", ctypes.c_double),
+                ("eps", ctypes.c_double), ("cfl", ctypes.c_double), ("adv_speed", ctypes.c_double)]
+
+
+_lib = None
+
+# exported symbol -> (restype, argtypes)
+_P = ctypes.c_void_p
+_SIGS = {
+    "teno_default_opts": (None, [_P]),
+    "teno_status_str": (ctypes.c_char_p, [ctypes.c_int]),
+    "teno_create": (ctypes.c_int, [_P, _P, _P, _P]),
+    "teno_destroy": (ctypes.c_int, [_P]),
+    "teno_state_elems": (ctypes.c_size_t, [_P]),
+    "teno_nfaces": (ctypes.c_size_t, [_P]),
+    "teno_set_stream": (ctypes.c_int, [_P, _P]),
+    "teno_rhs": (ctypes.c_int, [_P, _P, _P, _P]),
+    "teno_face_fluxes": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P]),
+    "teno_rhs_frozen": (ctypes.c_int, [_P, _P, _P, _P, _P]),
+    "teno_step": (ctypes.c_int, [_P, _P, ctypes.c_double]),
+    "teno_run": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.c_double, ctypes.c_int32]),
+    "teno_poll": (ctypes.c_int, [_P]),
+    "teno_last_dt": (ctypes.c_int, [_P, _P]),
+    "teno_set_timing": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "teno_read_timing": (ctypes.c_int, [_P, _P, _P]),
+    "teno_rhs_vjp": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
+    "teno_run_record": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, _P, _P, _P]),
+    "teno_run_replay": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P, _P]),
+    "teno_run_vjp": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int32, ctypes.c_int32, _P]),
+    "teno_batch_create": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P]),
+    "teno_batch_destroy": (ctypes.c_int, [_P]),
+    "teno_batch_total_elems": (ctypes.c_size_t, [_P]),
+    "teno_batch_offset": (ctypes.c_size_t, [_P, ctypes.c_int32]),
+    "teno_batch_run": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.c_int32]),
+    "teno_batch_poll": (ctypes.c_int, [_P]),
+}
+
+
+def lib():
+    """Load libteno.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1808_00037_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(code, where):
+    if code != 0:
+        raise TenoError(code, where)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def default_opts():
+    o = Opts()
+    lib().teno_default_opts(ctypes.byref(o))
+    return o
+
+
+class Solver:
+    """One problem instance on the current GPU: grid, boundary conditions and scheme options."""
+
+    def __init__(self, sys, nx, ny=1, x0=0.0, x1=1.0, y0=0.0, y1=1.0, bc_x=PERIODIC, bc_y=PERIODIC,
+                 dtype=torch.float64, scheme=TENO7X, alpha_mode=0, eps=None, gamma=1.4, ct=1e-5,
+                 cfl=0.5, adv_speed=1.0):
+        self.sys, self.nx, self.ny = sys, nx, ny
+        self.dtype = dtype
+        self.nvar = NVAR[sys]
+        g = Grid(sys, nx, ny, bc_x, bc_y, F64 if dtype == torch.float64 else F32, x0, x1, y0, y1)
+        o = default_opts()
+        o.scheme, o.alpha_mode, o.gamma, o.ct, o.cfl, o.adv_speed = scheme, alpha_mode, gamma, ct, cfl, adv_speed
+        if eps is not None:
+            o.eps_mode, o.eps = 1, float(eps)
+        self.grid, self.opts = g, o
+        self._stream_val = torch.cuda.current_stream().cuda_stream
+        h = ctypes.c_void_p()
+        _check(lib().teno_create(ctypes.byref(g), ctypes.byref(o), _stream(), ctypes.byref(h)), "teno_create")
+        self._h = h
+        self.nfaces = lib().teno_nfaces(h)
+        self.nfaces_x = ny * (nx + 1)
+
+    @classmethod
+    def for_problem(cls, pr, dtype=torch.float64, **kw):
+        """Build from a workloads.Problem."""
+        return cls(pr.sys, pr.nx, pr.ny, pr.x0, pr.x1, pr.y0, pr.y1, pr.bc_x, pr.bc_y, dtype=dtype,
+                   cfl=pr.cfl, gamma=pr.gamma, **kw)
+
+    @property
+    def shape(self):
+        return (self.nvar, self.ny, self.nx)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().teno_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _sync_stream(self):
+        s = torch.cuda.current_stream().cuda_stream
+        if s != self._stream_val:
+            _check(lib().teno_set_stream(self._h, ctypes.c_void_p(s)), "teno_set_stream")
+            self._stream_val = s
+
+    def _state(self, U):
+        if not (U.is_cuda and U.dtype == self.dtype and U.is_contiguous() and tuple(U.shape) == self.shape):
+            raise ValueError(f"state must be a contiguous {self.dtype} CUDA tensor of shape {self.shape}")
+        return U
+
+    def empty_state(self):
+        return torch.empty(self.shape, dtype=self.dtype, device="cuda")
+
+    def masks_buffer(self):
+        return torch.empty(self.nfaces, dtype=torch.int32, device="cuda")
+
+    def rhs(self, U, out=None, masks=None):
+        self._sync_stream()
+        U = self._state(U)
+        out = self.empty_state() if out is None else self._state(out)
+        _check(lib().teno_rhs(self._h, _ptr(U), _ptr(out), _ptr(masks)), "teno_rhs")
+        return out
+
+    def face_fluxes(self, U):
+        """Face fluxes, mask and flag words and the Lax-Friedrichs constants of one evaluation."""
+        self._sync_stream()
+        U = self._state(U)
+        nv, nx, ny = self.nvar, self.nx, self.ny
+        Fx = torch.empty((nv, ny, nx + 1), dtype=self.dtype, device="cuda")
+        Fy = torch.empty((nv, ny + 1, nx), dtype=self.dtype, device="cuda") if self.sys == EULER2D else None
+        masks = torch.empty(self.nfaces, dtype=torch.int32, device="cuda")
+        flags = torch.empty(self.nfaces, dtype=torch.int32, device="cuda")
+        alpha = torch.zeros(8, dtype=torch.float64, device="cuda")
+        _check(lib().teno_face_fluxes(self._h, _ptr(U), _ptr(Fx), _ptr(Fy), _ptr(masks), _ptr(flags), _ptr(alpha)),
+               "teno_face_fluxes")
+        out = dict(Fx=Fx, masks=masks, flags=flags, alpha=alpha)
+        if Fy is not None:
+            out["Fy"] = Fy
+        return out
+
+    def rhs_frozen(self, U, masks, alpha, out=None):
+        self._sync_stream()
+        U = self._state(U)
+        out = self.empty_state() if out is None else self._state(out)
+        _check(lib().teno_rhs_frozen(self._h, _ptr(U), _ptr(masks), _ptr(alpha), _ptr(out)), "teno_rhs_frozen")
+        return out
+
+    def step(self, U, dt=0.0):
+        self._sync_stream()
+        _check(lib().teno_step(self._h, _ptr(self._state(U)), float(dt)), "teno_step")
+        return U
+
+    def run(self, U, nsteps, dt=0.0, graph=True):
+        self._sync_stream()
+        _check(lib().teno_run(self._h, _ptr(self._state(U)), int(nsteps), float(dt), 1 if graph else 0), "teno_run")
+        return U
+
+    def poll(self):
+        _check(lib().teno_poll(self._h), "device status")
+
+    def last_dt(self):
+        v = ctypes.c_double()
+        _check(lib().teno_last_dt(self._h, ctypes.byref(v)), "teno_last_dt")
+        return v.value
+
+    def set_timing(self, enable=True):
+        _check(lib().teno_set_timing(self._h, 1 if enable else 0), "teno_set_timing")
+
+    def read_timing(self):
+        """{kind: (total ms, launches)} for kind 'x' (x-sweep [+ RK stage]) and 'y' (y-sweep)."""
+        ms = (ctypes.c_double * 2)()
+        cnt = (ctypes.c_int32 * 2)()
+        _check(lib().teno_read_timing(self._h, ms, cnt), "teno_read_timing")
+        return {"x": (ms[0], cnt[0]), "y": (ms[1], cnt[1])}
+
+    # ------------------------------------------------------------------ frozen-selection adjoint
+    def rhs_vjp(self, U, masks, alpha, lam, out=None):
+        self._sync_stream()
+        out = self.empty_state() if out is None else out
+        _check(lib().teno_rhs_vjp(self._h, _ptr(self._state(U)), _ptr(masks), _ptr(alpha), _ptr(self._state(lam)),
+                                  _ptr(out)), "teno_rhs_vjp")
+        return out
+
+    def run_record(self, U, nsteps, ckpt_every, dt=0.0, record_masks=True):
+        """Advance U in place; returns the recording (checkpoints, masks, alpha/dt)."""
+        self._sync_stream()
+        nck = nsteps // ckpt_every + 1
+        ckpt = torch.empty((nck,) + self.shape, dtype=self.dtype, device="cuda")
+        masks = torch.empty((nsteps, 3, self.nfaces), dtype=torch.int32, device="cuda") if record_masks else None
+        ad = torch.empty((nsteps, 25), dtype=torch.float64, device="cuda")
+        _check(lib().teno_run_record(self._h, _ptr(self._state(U)), int(nsteps), float(dt), int(ckpt_every),
+                                     _ptr(ckpt), _ptr(masks), _ptr(ad)), "teno_run_record")
+        return dict(ckpt=ckpt, masks=masks, alpha_dt=ad, nsteps=nsteps, ckpt_every=ckpt_every)
+
+    def run_replay(self, U, rec, nsteps=None):
+        self._sync_stream()
+        n = rec["nsteps"] if nsteps is None else nsteps
+        _check(lib().teno_run_replay(self._h, _ptr(self._state(U)), int(n), _ptr(rec["masks"]), _ptr(rec["alpha_dt"])),
+               "teno_run_replay")
+        return U
+
+    def run_vjp(self, rec, lam):
+        """lam: dJ/dU(T) (overwritten in place with dJ/dU(0))."""
+        self._sync_stream()
+        _check(lib().teno_run_vjp(self._h, _ptr(rec["ckpt"]), _ptr(rec["masks"]), _ptr(rec["alpha_dt"]),
+                                  int(rec["nsteps"]), int(rec["ckpt_every"]), _ptr(self._state(lam))), "teno_run_vjp")
+        return lam
+
+
+class Batch:
+    """Many independent Euler problems advanced together (one packed state buffer)."""
+
+    def __init__(self, problems, dtype=torch.float64, cfl=0.5, gamma=1.4):
+        n = len(problems)
+        grids = (Grid * n)()
+        for k, pr in enumerate(problems):
+            grids[k] = Grid(pr.sys, pr.nx, pr.ny, pr.bc_x, pr.bc_y, F64 if dtype == torch.float64 else F32,
+                            pr.x0, pr.x1, pr.y0, pr.y1)
+        o = default_opts()
+        o.cfl, o.gamma = cfl, gamma
+        self.dtype = dtype
+        self.problems = problems
+        self._stream_val = torch.cuda.current_stream().cuda_stream
+        h = ctypes.c_void_p()
+        _check(lib().teno_batch_create(grids, n, ctypes.byref(o), _stream(), ctypes.byref(h)), "teno_batch_create")
+        self._h = h
+        self.total = lib().teno_batch_total_elems(h)
+        self.offsets = [lib().teno_batch_offset(h, k) for k in range(n)]
+
+    def pack(self, states):
+        buf = torch.empty(self.total, dtype=self.dtype, device="cuda")
+        for off, U in zip(self.offsets, states):
+            buf[off:off + U.numel()] = U.reshape(-1).to(device="cuda", dtype=self.dtype)
+        return buf
+
+    def unpack(self, buf, k):
+        pr = self.problems[k]
+        nv = NVAR[pr.sys]
+        off = self.offsets[k]
+        return buf[off:off + nv * pr.ny * pr.nx].view(nv, pr.ny, pr.nx)
+
+    def run(self, buf, nsteps, mode=0):
+        if torch.cuda.current_stream().cuda_stream != self._stream_val:
+            raise RuntimeError("a Batch runs on the stream it was created on")
+        _check(lib().teno_batch_run(self._h, _ptr(buf), int(nsteps), int(mode)), "teno_batch_run")
+        return buf
+
+    def poll(self):
+        _check(lib().teno_batch_poll(self._h), "batch device status")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().teno_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
