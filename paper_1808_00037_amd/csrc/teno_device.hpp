@@ -34,7 +34,10 @@ constexpr int BLOCK = 256;
 constexpr int SEG_CELLS = 61;   // cells finished per segment
 constexpr int SEG_HALO = 5;     // first staged cell is c0 - 5
 constexpr int SEG_LOAD = 72;    // staged cells per segment (faces c0-1..c0+62 read c0-5..c0+65)
-constexpr int NSEG_X = 4;       // segments per block, x-sweeps (one per wave)
+#ifndef TENO_NSEG_X
+#define TENO_NSEG_X 4
+#endif
+constexpr int NSEG_X = TENO_NSEG_X;  // segments per block, x-sweeps
 constexpr int NSEG_Y = 8;       // columns per block, y-sweeps (two per wave)
 constexpr int NCOPY = 64;       // spread copies of the wave-speed maxima (atomic contention)
 constexpr int NWORD = 16;       // words per copy: 0-3 x fields, 4-7 y fields, 8 CFL denominator
@@ -113,6 +116,20 @@ __device__ constexpr Rat COEF[NCOEF_ROWS][7] = {
 // (at least one chi_k >= 1/3 > C_T); it maps to the full stencil and is reported as an error.
 __device__ constexpr int TENO5_ROW[8] = {13, 16, 17, 14, 18, 19, 15, 13};
 
+// Table 2 row 0 applied to seven upwind-ordered values, constants folded at compile time.
+template <typename T>
+__device__ __forceinline__ T recon_row0(T w0, T w1, T w2, T w3, T w4, T w5, T w6)
+{
+    T h = T(-1.0 / 140.0) * w0;
+    h += T(5.0 / 84.0) * w1;
+    h += T(-101.0 / 420.0) * w2;
+    h += T(319.0 / 420.0) * w3;
+    h += T(107.0 / 210.0) * w4;
+    h += T(-19.0 / 210.0) * w5;
+    h += T(1.0 / 105.0) * w6;
+    return h;
+}
+
 // Table 3 as printed: neighbour vector (a,b,c,d,e) = (delta_{i-1,0}, delta_{i,0}, delta_{i,1},
 // delta_{i,2}, delta_{i+1,2}) -> Table 2 row; '*' matches 0 or 1; (*,0,0,0,*) has no stencil.
 struct Pattern { const char *p; int m; };
@@ -153,26 +170,56 @@ __device__ __forceinline__ int table3(unsigned idx)
 
 // ------------------------------------------------------------------------------------------------
 // Five-point cut-off of one split side (eq:smooth_expl, eq:tau5, eq:TENO1 with C = 1, q = 6,
-// eq:norm, eq:seclect). Returns bit k = delta_k. (a..e) = values at i-2..i+2 in upwind order.
-// delta_k = 0 iff gamma_k / sum(gamma) < C_T, evaluated as gamma_k < C_T * sum(gamma) with
-// gamma_k = (1 + tau (D_j D_l) / (D0 D1 D2))^6, D_k = beta_k + eps: one division per side instead
-// of six; equal to the definition up to rounding (so flags can differ only when chi_k lies within
-// rounding of C_T).
+// eq:norm, eq:seclect). (a..e) = values at i-2..i+2 in upwind order.
+//
+// smooth5() computes beta_0..2 and tau5 = |beta_0 - beta_2|. Exact shortcut: with
+// r_k = 1 + tau5/(beta_k + eps) >= 1, the smallest chi_k is at least
+// 1 / (1 + 2 (r_max/r_min)^6); if tau5 <= 5 (min_k beta_k + eps) then r_max/r_min <= 6 and
+// chi_min >= 1/93313 > C_T (1e-5) with a 7% margin, so every delta_k = 1 whatever the rounding.
+// cutoff3() evaluates the definition: delta_k = 0 iff gamma_k / sum(gamma) < C_T, computed as
+// gamma_k < C_T * sum(gamma) with gamma_k = (1 + tau (D_j D_l) / (D0 D1 D2))^6, D_k = beta_k + eps:
+// one reciprocal per side instead of six divisions; equal to the definition up to rounding, so a
+// flag can differ from a straight evaluation only when chi_k lies within rounding of C_T.
 // ------------------------------------------------------------------------------------------------
-__device__ __forceinline__ unsigned cutoff3(double a, double b, double c, double d, double e,
-                                            double eps, double ct)
+template <typename T> struct Smooth { T b0, b1, b2, tau; };
+
+template <typename T>
+__device__ __forceinline__ Smooth<T> smooth5(T a, T b, T c, T d, T e)
 {
-    double t0 = a - 4.0 * b + 3.0 * c, t1 = a - 2.0 * b + c;
-    double t2 = b - d, t3 = b - 2.0 * c + d;
-    double t4 = 3.0 * c - 4.0 * d + e, t5 = c - 2.0 * d + e;
-    double b0 = 0.25 * t0 * t0 + (13.0 / 12.0) * t1 * t1;
-    double b1 = 0.25 * t2 * t2 + (13.0 / 12.0) * t3 * t3;
-    double b2 = 0.25 * t4 * t4 + (13.0 / 12.0) * t5 * t5;
-    double tau = fabs(b0 - b2);
-    double D0 = b0 + eps, D1 = b1 + eps, D2 = b2 + eps;
+    T t0 = a - T(4) * b + T(3) * c, t1 = a - T(2) * b + c;
+    T t2 = b - d, t3 = b - T(2) * c + d;
+    T t4 = T(3) * c - T(4) * d + e, t5 = c - T(2) * d + e;
+    Smooth<T> r;
+    r.b0 = T(0.25) * t0 * t0 + T(13.0 / 12.0) * t1 * t1;
+    r.b1 = T(0.25) * t2 * t2 + T(13.0 / 12.0) * t3 * t3;
+    r.b2 = T(0.25) * t4 * t4 + T(13.0 / 12.0) * t5 * t5;
+    r.tau = fabs(r.b0 - r.b2);
+    return r;
+}
+
+template <typename T>
+__device__ __forceinline__ bool all_smooth(const Smooth<T> &m, T eps)
+{
+    T bmin = fmin(m.b0, fmin(m.b1, m.b2));
+    return m.tau <= T(5) * (bmin + eps);
+}
+
+// Reciprocal from the hardware estimate and two Newton steps (argument normal and positive).
+__device__ __forceinline__ double recip(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+__device__ __forceinline__ float recip(float x) { return 1.0f / x; }
+
+__device__ __forceinline__ unsigned cutoff3(const Smooth<double> &m, double eps, double ct)
+{
+    double D0 = m.b0 + eps, D1 = m.b1 + eps, D2 = m.b2 + eps;
     double D01 = D0 * D1;
-    double inv = 1.0 / (D01 * D2);
-    double tinv = tau * inv;
+    double tinv = m.tau * recip(D01 * D2);
     double r0 = 1.0 + tinv * (D1 * D2);
     double r1 = 1.0 + tinv * (D0 * D2);
     double r2 = 1.0 + tinv * D01;
@@ -185,16 +232,9 @@ __device__ __forceinline__ unsigned cutoff3(double a, double b, double c, double
 }
 
 // Single precision: gamma_k / gamma_max keeps every term in [0, 1] (no overflow of r^6).
-__device__ __forceinline__ unsigned cutoff3(float a, float b, float c, float d, float e, float eps, float ct)
+__device__ __forceinline__ unsigned cutoff3(const Smooth<float> &m, float eps, float ct)
 {
-    float t0 = a - 4.0f * b + 3.0f * c, t1 = a - 2.0f * b + c;
-    float t2 = b - d, t3 = b - 2.0f * c + d;
-    float t4 = 3.0f * c - 4.0f * d + e, t5 = c - 2.0f * d + e;
-    float b0 = 0.25f * t0 * t0 + (13.0f / 12.0f) * t1 * t1;
-    float b1 = 0.25f * t2 * t2 + (13.0f / 12.0f) * t3 * t3;
-    float b2 = 0.25f * t4 * t4 + (13.0f / 12.0f) * t5 * t5;
-    float tau = fabsf(b0 - b2);
-    float r0 = 1.0f + tau / (b0 + eps), r1 = 1.0f + tau / (b1 + eps), r2 = 1.0f + tau / (b2 + eps);
+    float r0 = 1.0f + m.tau / (m.b0 + eps), r1 = 1.0f + m.tau / (m.b1 + eps), r2 = 1.0f + m.tau / (m.b2 + eps);
     float rm = fmaxf(r0, fmaxf(r1, r2));
     float q0 = r0 / rm, q1 = r1 / rm, q2 = r2 / rm;
     float g0 = q0 * q0 * q0, g1 = q1 * q1 * q1, g2 = q2 * q2 * q2;
@@ -203,6 +243,54 @@ __device__ __forceinline__ unsigned cutoff3(float a, float b, float c, float d, 
     g2 *= g2;
     float thr = ct * ((g0 + g1) + g2);
     return (g0 < thr ? 0u : 1u) | (g1 < thr ? 0u : 2u) | (g2 < thr ? 0u : 4u);
+}
+
+// Roe-averaged quantities of one face and the rows/columns of its eigenvector matrices.
+template <typename T> struct Roe {
+    T un = T(0), ut = T(0), cs = T(1), ic = T(1), H = T(0), q2 = T(0), b1 = T(0), b2 = T(0);
+};
+
+// Left eigenvector (row s of L) and right eigenvector (column s of R) of the flux Jacobian at the
+// Roe state, in local variable order (rho, m_n, [m_t], E). Fields: u_n - c, u_n (entropy),
+// [u_n (shear)], u_n + c. With b1 = (gamma-1)/c^2 and b2 = b1 |u|^2 / 2, L R = I.
+// Scalar systems: L = R = 1.
+template <typename T, int NV>
+__device__ __forceinline__ void char_basis(const Roe<T> &r, int s, T L[NV], T R[NV])
+{
+    if constexpr (NV == 1) {
+        L[0] = T(1);
+        R[0] = T(1);
+    } else {
+        const T h = T(0.5);
+        // map the 1D fields (0, 1, 2) onto the 2D ones (0, 1, 3)
+        const int s4 = (NV == 3 && s == 2) ? 3 : s;
+        T l0, l1, l2 = T(0), l3, r0, r1, r2 = T(0), r3;
+        switch (s4) {
+        case 0:
+            l0 = h * (r.b2 + r.un * r.ic); l1 = -h * (r.b1 * r.un + r.ic); l2 = -h * r.b1 * r.ut; l3 = h * r.b1;
+            r0 = T(1); r1 = r.un - r.cs; r2 = r.ut; r3 = r.H - r.un * r.cs;
+            break;
+        case 1:
+            l0 = T(1) - r.b2; l1 = r.b1 * r.un; l2 = r.b1 * r.ut; l3 = -r.b1;
+            r0 = T(1); r1 = r.un; r2 = r.ut; r3 = h * r.q2;
+            break;
+        case 2:
+            l0 = -r.ut; l1 = T(0); l2 = T(1); l3 = T(0);
+            r0 = T(0); r1 = T(0); r2 = T(1); r3 = r.ut;
+            break;
+        default:
+            l0 = h * (r.b2 - r.un * r.ic); l1 = -h * (r.b1 * r.un - r.ic); l2 = -h * r.b1 * r.ut; l3 = h * r.b1;
+            r0 = T(1); r1 = r.un + r.cs; r2 = r.ut; r3 = r.H + r.un * r.cs;
+            break;
+        }
+        if constexpr (NV == 3) {
+            L[0] = l0; L[1] = l1; L[2] = l3;
+            R[0] = r0; R[1] = r1; R[2] = r3;
+        } else {
+            L[0] = l0; L[1] = l1; L[2] = l2; L[3] = l3;
+            R[0] = r0; R[1] = r1; R[2] = r2; R[3] = r3;
+        }
+    }
 }
 
 template <typename T> __device__ __forceinline__ T shfl_up1(T v) { return __shfl_up(v, 1, WAVE); }
@@ -304,8 +392,18 @@ __device__ __forceinline__ void block_max_atomic(double w[9], unsigned long long
 //   DIR: 0 = x (lines are rows), 1 = y (lines are columns).
 //   FROZEN: the selection is read from masks_in instead of being measured.
 // ------------------------------------------------------------------------------------------------
+// Register budget of the sweep kernels: the minimum number of waves per SIMD the compiler must fit.
+// Measured on MI355X (2D Euler, FP64, 4096^2): 3 for both directions (the y-sweep's 8-column LDS
+// tile admits at most three blocks per CU; 4 makes the x-sweep spill).
+#ifndef TENO_MIN_WAVES_X
+#define TENO_MIN_WAVES_X 3
+#endif
+#ifndef TENO_MIN_WAVES_Y
+#define TENO_MIN_WAVES_Y 3
+#endif
+
 template <typename T, int SYS, int DIR, bool FROZEN>
-__global__ void __launch_bounds__(BLOCK) sweep_kernel(SweepArgs<T> a)
+__global__ void __launch_bounds__(BLOCK, DIR == 0 ? TENO_MIN_WAVES_X : TENO_MIN_WAVES_Y) sweep_kernel(SweepArgs<T> a)
 {
     constexpr int NV = Sys<SYS>::NV;
     constexpr int NREC = Sys<SYS>::NREC;
@@ -402,119 +500,150 @@ __global__ void __launch_bounds__(BLOCK) sweep_kernel(SweepArgs<T> a)
         for (int v = 0; v < NV; ++v) Fh[v] = T(0);
         uint32_t mword = 0, fword = 0;
 
-        // characteristic basis at the face (Roe average of cells i = q k+3 and i+1 = q k+4)
-        T Lm[NV][NV], Rm[NV][NV];
-        if constexpr (!EULER) {
-            Lm[0][0] = T(1);
-            Rm[0][0] = T(1);
-        } else {
+        // epilogue operands (RK base state, other direction's part) fetched now, consumed after
+        // the face computation, so that their latency overlaps it
+        // (x-sweeps only: the y-sweep never has either)
+        T pre0[NV], pre1[NV];
+        const size_t coff = DIR == 0 ? (size_t)line * a.nx + f : (size_t)f * a.nx + line;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const size_t go = (size_t)gvar<SYS, DIR>(v) * ncell + coff;
+            pre0[v] = (DIR == 0 && cell_ok && a.mode == MODE_STAGE) ? a.U0[go] : T(0);
+            pre1[v] = (DIR == 0 && cell_ok && a.addend) ? a.addend[go] : T(0);
+        }
+
+        // Roe-averaged state of the face (cells i = q k+3 and i+1 = q k+4, Remark 3)
+        Roe<T> roe;
+        if constexpr (EULER) {
             using S = Sys<SYS>;
             const T gm1 = a.gamma - T(1);
             T sL = R0[SEG_LOAD * S::S + k + 3], sR = R0[SEG_LOAD * S::S + k + 4];
             T isum = T(1) / (sL + sR);
-            T un = (sL * R0[SEG_LOAD * S::UN + k + 3] + sR * R0[SEG_LOAD * S::UN + k + 4]) * isum;
-            T ut = T(0);
-            if constexpr (NV == 4) ut = (sL * R0[SEG_LOAD * S::UT + k + 3] + sR * R0[SEG_LOAD * S::UT + k + 4]) * isum;
-            T H = (sL * R0[SEG_LOAD * S::H + k + 3] + sR * R0[SEG_LOAD * S::H + k + 4]) * isum;
-            T q2 = un * un + ut * ut;
-            T c2 = gm1 * (H - T(0.5) * q2);
+            roe.un = (sL * R0[SEG_LOAD * S::UN + k + 3] + sR * R0[SEG_LOAD * S::UN + k + 4]) * isum;
+            roe.ut = T(0);
+            if constexpr (NV == 4)
+                roe.ut = (sL * R0[SEG_LOAD * S::UT + k + 3] + sR * R0[SEG_LOAD * S::UT + k + 4]) * isum;
+            roe.H = (sL * R0[SEG_LOAD * S::H + k + 3] + sR * R0[SEG_LOAD * S::H + k + 4]) * isum;
+            roe.q2 = roe.un * roe.un + roe.ut * roe.ut;
+            T c2 = gm1 * (roe.H - T(0.5) * roe.q2);
             if (face_ok && !(c2 > T(0))) bad |= isfinite(c2) ? ERR_NONPHYSICAL : ERR_NONFINITE;
-            T cs = sqrt(c2);
-            T ic = T(1) / cs;
-            T b1 = gm1 * ic * ic;
-            T b2 = T(0.5) * b1 * q2;
-            T hb1 = T(0.5) * b1;
-            if constexpr (NV == 3) {
-                Lm[0][0] = T(0.5) * (b2 + un * ic); Lm[0][1] = -T(0.5) * (b1 * un + ic); Lm[0][2] = hb1;
-                Lm[1][0] = T(1) - b2;               Lm[1][1] = b1 * un;                  Lm[1][2] = -b1;
-                Lm[2][0] = T(0.5) * (b2 - un * ic); Lm[2][1] = -T(0.5) * (b1 * un - ic); Lm[2][2] = hb1;
-                Rm[0][0] = T(1);          Rm[0][1] = T(1);            Rm[0][2] = T(1);
-                Rm[1][0] = un - cs;       Rm[1][1] = un;              Rm[1][2] = un + cs;
-                Rm[2][0] = H - un * cs;   Rm[2][1] = T(0.5) * q2;     Rm[2][2] = H + un * cs;
-            } else {
-                Lm[0][0] = T(0.5) * (b2 + un * ic); Lm[0][1] = -T(0.5) * (b1 * un + ic);
-                Lm[0][2] = -hb1 * ut;               Lm[0][3] = hb1;
-                Lm[1][0] = T(1) - b2; Lm[1][1] = b1 * un; Lm[1][2] = b1 * ut; Lm[1][3] = -b1;
-                Lm[2][0] = -ut; Lm[2][1] = T(0); Lm[2][2] = T(1); Lm[2][3] = T(0);
-                Lm[3][0] = T(0.5) * (b2 - un * ic); Lm[3][1] = -T(0.5) * (b1 * un - ic);
-                Lm[3][2] = -hb1 * ut;               Lm[3][3] = hb1;
-                Rm[0][0] = T(1);        Rm[0][1] = T(1);        Rm[0][2] = T(0); Rm[0][3] = T(1);
-                Rm[1][0] = un - cs;     Rm[1][1] = un;          Rm[1][2] = T(0); Rm[1][3] = un + cs;
-                Rm[2][0] = ut;          Rm[2][1] = ut;          Rm[2][2] = T(1); Rm[2][3] = ut;
-                Rm[3][0] = H - un * cs; Rm[3][1] = T(0.5) * q2; Rm[3][2] = ut;   Rm[3][3] = H + un * cs;
-            }
+            roe.cs = sqrt(c2);
+            roe.ic = T(1) / roe.cs;
+            roe.b1 = gm1 * roe.ic * roe.ic;
+            roe.b2 = T(0.5) * roe.b1 * roe.q2;
         }
 
-#pragma unroll
+        // Characteristic fields one at a time (kept as a loop: only one field's split values are
+        // live, which keeps the wave's register budget low enough for several waves per SIMD).
+#pragma unroll 1
         for (int sf = 0; sf < NV; ++sf) {
+            asm volatile("" ::: "memory");      // keep the stencil reads inside the field loop
             const T al = (T)alpha[sf];
+            T Ls[NV], Rs[NV];
+            char_basis<T, NV>(roe, sf, Ls, Rs);
+            // the 1/2 of the splitting folded into L (exact scaling)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) Ls[v] *= T(0.5);
             T vp[8], vm[8];
+            if (NV == 4 && sf == 2) {
+                // shear field: L_2 = (-u_t, 0, 1, 0), so L_2 U = m_t - u_t rho and L_2 F = u_n L_2 U
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int q = k + j;
-                T lu, lf;
-                if constexpr (!EULER) {
-                    T u = R0[q];
-                    lu = u;
-                    lf = SYS == ADV1D ? a.adv * u : T(0.5) * u * u;
-                } else {
-                    using S = Sys<SYS>;
-                    T un = R0[SEG_LOAD * S::UN + q], p = R0[SEG_LOAD * S::P + q];
-                    lu = Lm[sf][0] * R0[q];
-#pragma unroll
-                    for (int v = 1; v < NV; ++v) lu += Lm[sf][v] * R0[SEG_LOAD * v + q];
-                    // L_s F = u_n (L_s U) + p (L_s[n] + u_n L_s[E]): F = u_n U + p (0, 1, 0, u_n)
-                    lf = un * lu + p * (Lm[sf][1] + un * Lm[sf][NV - 1]);
+                for (int j = 0; j < 8; ++j) {
+                    const int q = k + j;
+                    T lu = R0[SEG_LOAD * 2 + q] * Ls[2] + Ls[0] * R0[q];
+                    T lf = R0[SEG_LOAD * Sys<EULER2D>::UN + q] * lu;
+                    vp[j] = lf + al * lu;
+                    vm[j] = lf - al * lu;
                 }
-                vp[j] = T(0.5) * (lf + al * lu);
-                vm[j] = T(0.5) * (lf - al * lu);
+            } else {
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const int q = k + j;
+                    T lu, lf;
+                    if constexpr (!EULER) {
+                        T u = R0[q];
+                        lu = T(0.5) * u;
+                        lf = SYS == ADV1D ? a.adv * lu : lu * u * T(0.5);
+                    } else {
+                        using S = Sys<SYS>;
+                        T un = R0[SEG_LOAD * S::UN + q], p = R0[SEG_LOAD * S::P + q];
+                        lu = Ls[0] * R0[q];
+#pragma unroll
+                        for (int v = 1; v < NV; ++v) lu += Ls[v] * R0[SEG_LOAD * v + q];
+                        // L_s F = u_n (L_s U) + p (L_s[n] + u_n L_s[E]): F = u_n U + p (0, 1, 0, u_n)
+                        lf = un * lu + p * (Ls[1] + un * Ls[NV - 1]);
+                    }
+                    vp[j] = lf + al * lu;
+                    vm[j] = lf - al * lu;
+                }
             }
 
-            int mp, mm;
+            int mp = 0, mm = 0;
             if constexpr (FROZEN) {
                 mp = (int)((mword_in >> (8 * sf)) & 15u);
                 mm = (int)((mword_in >> (8 * sf + 4)) & 15u);
                 if (a.scheme == 1) { mp = TENO5_ROW[mp & 7]; mm = TENO5_ROW[mm & 7]; }
             } else {
-                unsigned dp = cutoff3(vp[1], vp[2], vp[3], vp[4], vp[5], a.eps, a.ct);
-                unsigned dm = cutoff3(vm[6], vm[5], vm[4], vm[3], vm[2], a.eps, a.ct);
-                unsigned bits = dp | (dm << 3);
-                fword |= bits << (6 * sf);
-                if (a.scheme == 0) {
-                    unsigned left = shfl_up1(bits), right = shfl_dn1(bits);
-                    // Delta+ = (d+_{i-1,0}, d+_{i,0}, d+_{i,1}, d+_{i,2}, d+_{i+1,2})
-                    unsigned ip = ((left & 1u) << 4) | ((dp & 1u) << 3) | ((dp & 2u) << 1) | ((dp & 4u) >> 1)
-                                | ((right >> 2) & 1u);
-                    // Delta- (mirror) = (d-_{i+1,0}, d-_{i,0}, d-_{i,1}, d-_{i,2}, d-_{i-1,2})
-                    unsigned im = (((right >> 3) & 1u) << 4) | ((dm & 1u) << 3) | ((dm & 2u) << 1)
-                                | ((dm & 4u) >> 1) | ((left >> 5) & 1u);
-                    mp = table3(ip);
-                    mm = table3(im);
-                    if (face_ok && (mp == 15 || mm == 15)) bad |= ERR_SELECTION;
-                    mp = mp == 15 ? 0 : mp;
-                    mm = mm == 15 ? 0 : mm;
-                    mword |= (uint32_t)(mp | (mm << 4)) << (8 * sf);
+                Smooth<T> sp = smooth5(vp[1], vp[2], vp[3], vp[4], vp[5]);
+                Smooth<T> sm = smooth5(vm[6], vm[5], vm[4], vm[3], vm[2]);
+                const bool easy = all_smooth(sp, a.eps) && all_smooth(sm, a.eps);
+                if (__all(easy)) {
+                    // every flag of every face of the wave is 1: the full stencil on both sides
+                    fword |= 63u << (6 * sf);
+                    if (a.scheme == 0) {
+                        mword |= 0u;
+                    } else {
+                        mword |= (uint32_t)(7 | (7 << 4)) << (8 * sf);
+                        mp = mm = TENO5_ROW[7];
+                    }
                 } else {
-                    int cp = (int)(((dp & 1u) << 2) | (dp & 2u) | ((dp >> 2) & 1u));
-                    int cm = (int)(((dm & 1u) << 2) | (dm & 2u) | ((dm >> 2) & 1u));
-                    if (face_ok && (cp == 0 || cm == 0)) bad |= ERR_SELECTION;
-                    mword |= (uint32_t)(cp | (cm << 4)) << (8 * sf);
-                    mp = TENO5_ROW[cp];
-                    mm = TENO5_ROW[cm];
+                    unsigned dp = easy ? 7u : cutoff3(sp, a.eps, a.ct);
+                    unsigned dm = easy ? 7u : cutoff3(sm, a.eps, a.ct);
+                    unsigned bits = dp | (dm << 3);
+                    fword |= bits << (6 * sf);
+                    if (a.scheme == 0) {
+                        unsigned left = shfl_up1(bits), right = shfl_dn1(bits);
+                        // Delta+ = (d+_{i-1,0}, d+_{i,0}, d+_{i,1}, d+_{i,2}, d+_{i+1,2})
+                        unsigned ip = ((left & 1u) << 4) | ((dp & 1u) << 3) | ((dp & 2u) << 1) | ((dp & 4u) >> 1)
+                                    | ((right >> 2) & 1u);
+                        // Delta- (mirror) = (d-_{i+1,0}, d-_{i,0}, d-_{i,1}, d-_{i,2}, d-_{i-1,2})
+                        unsigned im = (((right >> 3) & 1u) << 4) | ((dm & 1u) << 3) | ((dm & 2u) << 1)
+                                    | ((dm & 4u) >> 1) | ((left >> 5) & 1u);
+                        mp = table3(ip);
+                        mm = table3(im);
+                        if (face_ok && (mp == 15 || mm == 15)) bad |= ERR_SELECTION;
+                        mp = mp == 15 ? 0 : mp;
+                        mm = mm == 15 ? 0 : mm;
+                        mword |= (uint32_t)(mp | (mm << 4)) << (8 * sf);
+                    } else {
+                        int cp = (int)(((dp & 1u) << 2) | (dp & 2u) | ((dp >> 2) & 1u));
+                        int cm = (int)(((dm & 1u) << 2) | (dm & 2u) | ((dm >> 2) & 1u));
+                        if (face_ok && (cp == 0 || cm == 0)) bad |= ERR_SELECTION;
+                        mword |= (uint32_t)(cp | (cm << 4)) << (8 * sf);
+                        mp = TENO5_ROW[cp];
+                        mm = TENO5_ROW[cm];
+                    }
                 }
             }
-            const T *cp_ = coef + mp * 8;
-            const T *cm_ = coef + mm * 8;
-            T hp = cp_[0] * vp[0];
-            T hm = cm_[0] * vm[7];
+            T hp, hm;
+            if (__all(mp == 0 && mm == 0)) {
+                // Table 2 row 0 (the seventh-order linear scheme) as compile-time constants
+                hp = recon_row0<T>(vp[0], vp[1], vp[2], vp[3], vp[4], vp[5], vp[6]);
+                hm = recon_row0<T>(vm[7], vm[6], vm[5], vm[4], vm[3], vm[2], vm[1]);
+            } else {
+                const T *cp_ = coef + mp * 8;
+                const T *cm_ = coef + mm * 8;
+                hp = cp_[0] * vp[0];
+                hm = cm_[0] * vm[7];
 #pragma unroll
-            for (int l = 1; l < 7; ++l) {
-                hp += cp_[l] * vp[l];
-                hm += cm_[l] * vm[7 - l];
+                for (int l = 1; l < 7; ++l) {
+                    hp += cp_[l] * vp[l];
+                    hm += cm_[l] * vm[7 - l];
+                }
             }
             T w = hp + hm;
 #pragma unroll
-            for (int v = 0; v < NV; ++v) Fh[v] += Rm[v][sf] * w;
+            for (int v = 0; v < NV; ++v) Fh[v] += Rs[v] * w;
         }
 
         // ---- epilogue ----
@@ -542,13 +671,13 @@ __global__ void __launch_bounds__(BLOCK) sweep_kernel(SweepArgs<T> a)
                 for (int v = 0; v < NV; ++v) {
                     const size_t go = (size_t)gvar<SYS, DIR>(v) * ncell + off;
                     T d = -(Fr[v] - Fh[v]) * a.inv_h;
-                    if (a.addend) d = d + a.addend[go];
+                    if (a.addend) d = d + (DIR == 0 ? pre1[v] : a.addend[go]);
                     if (a.mode == MODE_RHS) {
                         a.out[go] = d;
                     } else {
                         // SSP-RK3 stage, Shu-Osher form
                         T uk = R0[SEG_LOAD * v + k + 4];   // staged record: conserved variable v first
-                        T u0 = a.U0[go];
+                        T u0 = DIR == 0 ? pre0[v] : a.U0[go];
                         T dt = (T)dtv;
                         T un;
                         if (a.stage == 0) un = u0 + dt * d;
