@@ -133,6 +133,10 @@ teno_status teno_poll(teno_ctx *ctx);
 /* dt of the most recent step (synchronises). */
 teno_status teno_last_dt(teno_ctx *ctx, double *dt_host);
 
+/* Copy (stream-ordered, no synchronisation) the eight Lax-Friedrichs constants of the most recent
+ * operator evaluation or stage to alpha_dev (device, 8 doubles: x fields then y fields). */
+teno_status teno_last_alpha(teno_ctx *ctx, double *alpha_dev);
+
 /* ------------------------------------------------------------------------------ measurement ----
  * Per-kernel timing with HIP events recorded on the context's stream around every sweep launch
  * (eager launches only; graph replays are not instrumented). kind 0 = x-sweep (with the RK stage
@@ -148,12 +152,13 @@ teno_status teno_read_timing(teno_ctx *ctx, double *ms, int32_t *count);
  * run (the selection is piecewise constant in U, so this is the derivative almost everywhere).
  * Only TENO_F64 contexts support them. */
 
-/* Vector-Jacobian product of the frozen operator at U: grad = (dL/dU)^T lam. Overwrites grad. */
+/* Vector-Jacobian product of the frozen operator at U: grad = (dL/dU)^T lam. Overwrites grad.
+ * Periodic directions need at least 8 cells (TENO_E_UNSUPPORTED otherwise). */
 teno_status teno_rhs_vjp(teno_ctx *ctx, const void *U, const uint32_t *masks, const double *alpha_dev,
                          const void *lam, void *grad);
 
 /* Forward run of nsteps steps that records what the adjoint needs: ckpt_dev holds
- * (nsteps/ckpt_every + 1) states (the state before steps 0, ckpt_every, 2*ckpt_every, ...),
+ * ceil(nsteps/ckpt_every) states (the state before steps 0, ckpt_every, 2*ckpt_every, ...),
  * masks_dev (nullable) nsteps*3*teno_nfaces() mask words, alpha_dt_dev nsteps*(3*8+1) doubles
  * (per step: the three stages' eight constants, then dt). U is advanced in place. */
 teno_status teno_run_record(teno_ctx *ctx, void *U, int32_t nsteps, double dt_fixed, int32_t ckpt_every,

@@ -732,7 +732,7 @@ __global__ void __launch_bounds__(BLOCK) wavespeed_kernel(const T *U, size_t nce
 //   frozen (nullable): replay the 8 constants (+ dt when stage == 0) from a recorded buffer.
 //   record (nullable): write the 8 constants (+ dt when stage == 0) to a recording buffer.
 // Recording layout per step: [stage0 alpha 8][stage1 alpha 8][stage2 alpha 8][dt].
-__global__ void prep_kernel(Ctrl *ctrl, int ring, int stage, double dt_fixed, double cfl, const double *frozen,
+static __global__ void prep_kernel(Ctrl *ctrl, int ring, int stage, double dt_fixed, double cfl, const double *frozen,
                             double *record)
 {
     __shared__ double vals[NWORD];
@@ -764,13 +764,13 @@ __global__ void prep_kernel(Ctrl *ctrl, int ring, int stage, double dt_fixed, do
     }
 }
 
-__global__ void clear_ring_kernel(Ctrl *ctrl, int ring)
+static __global__ void clear_ring_kernel(Ctrl *ctrl, int ring)
 {
     for (int q = threadIdx.x; q < NCOPY * NWORD; q += blockDim.x) (&ctrl->part[ring][0][0])[q] = 0ull;
 }
 
 // Copy the eight constants of the current stage out (parity/debug form).
-__global__ void copy_alpha_kernel(const Ctrl *ctrl, double *dst)
+static __global__ void copy_alpha_kernel(const Ctrl *ctrl, double *dst)
 {
     if (threadIdx.x < 8) dst[threadIdx.x] = ctrl->alpha[threadIdx.x];
 }

@@ -32,5 +32,26 @@ struct teno_ctx {
     size_t events_used = 0;
 };
 
+// One sweep launch request (see teno_lib.hip).
+struct SweepReq {
+    int dir;
+    int mode;
+    int stage;
+    bool frozen;
+    const void *U, *U0, *addend;
+    void *out, *Fout;
+    uint32_t *masks_out, *flags_out;
+    const uint32_t *masks_in;
+    const double *alpha;
+    unsigned long long *part;
+};
+
 bool teno_validate(const teno_grid *g, const teno_opts *o);
 void teno_fill_derived(teno_ctx *c);
+teno_status teno_ensure_scratch(teno_ctx *c);
+void teno_launch_sweep(teno_ctx *c, const SweepReq &r);
+void teno_launch_wavespeed(teno_ctx *c, const void *U, int ring);
+void teno_launch_prep(teno_ctx *c, int ring, int stage, double dt_fixed, const double *frozen, double *record);
+void teno_launch_clear(teno_ctx *c, int ring);
+void teno_enqueue_step(teno_ctx *c, void *U, double dt_fixed, const double *frozen_ad, double *record_ad,
+                       uint32_t *masks_rec, const uint32_t *masks_in, void **stage_states);

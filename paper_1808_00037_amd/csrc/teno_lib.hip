@@ -80,18 +80,6 @@ void teno_fill_derived(teno_ctx *c)
 // ------------------------------------------------------------------------------------------------
 // launch helpers
 // ------------------------------------------------------------------------------------------------
-struct SweepReq {
-    int dir;
-    int mode;
-    int stage;
-    bool frozen;
-    const void *U, *U0, *addend;
-    void *out, *Fout;
-    uint32_t *masks_out, *flags_out;
-    const uint32_t *masks_in;
-    const double *alpha;
-    unsigned long long *part;
-};
 
 // Event pair for the next instrumented launch of a kernel kind (null when timing is off or the
 // stream is being captured).
@@ -312,7 +300,7 @@ void teno_enqueue_step(teno_ctx *c, void *U, double dt_fixed, const double *froz
     }
 }
 
-static teno_status ensure_scratch(teno_ctx *c)
+teno_status teno_ensure_scratch(teno_ctx *c)
 {
     if (c->S1) return TENO_OK;
     size_t bytes = c->nelem * c->esize;
@@ -463,7 +451,7 @@ teno_status teno_face_fluxes(teno_ctx *c, const void *U, void *Fx, void *Fy, uin
 teno_status teno_step(teno_ctx *c, void *U, double dt_fixed)
 {
     if (!c || !U) return TENO_E_ARG;
-    teno_status st = ensure_scratch(c);
+    teno_status st = teno_ensure_scratch(c);
     if (st) return st;
     teno_launch_clear(c, 0);
     teno_launch_wavespeed(c, U, 0);
@@ -474,7 +462,7 @@ teno_status teno_step(teno_ctx *c, void *U, double dt_fixed)
 teno_status teno_run(teno_ctx *c, void *U, int32_t nsteps, double dt_fixed, int32_t use_graph)
 {
     if (!c || !U || nsteps < 0) return TENO_E_ARG;
-    teno_status st = ensure_scratch(c);
+    teno_status st = teno_ensure_scratch(c);
     if (st) return st;
     teno_launch_clear(c, 0);
     teno_launch_wavespeed(c, U, 0);
@@ -542,6 +530,13 @@ teno_status teno_read_timing(teno_ctx *c, double *ms, int32_t *count)
         count[k] += 1;
     }
     return TENO_OK;
+}
+
+teno_status teno_last_alpha(teno_ctx *c, double *alpha_dev)
+{
+    if (!c || !alpha_dev) return TENO_E_ARG;
+    hipLaunchKernelGGL(copy_alpha_kernel, dim3(1), dim3(64), 0, c->stream, c->ctrl_d, alpha_dev);
+    return hipGetLastError() == hipSuccess ? TENO_OK : TENO_E_HIP;
 }
 
 teno_status teno_last_dt(teno_ctx *c, double *dt_host)

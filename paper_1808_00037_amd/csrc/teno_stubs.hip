@@ -1,10 +1,6 @@
 // placeholder definitions (replaced by the adjoint and batching translation units)
 #include "teno.h"
 extern "C" {
-teno_status teno_rhs_vjp(teno_ctx *, const void *, const uint32_t *, const double *, const void *, void *) { return TENO_E_UNSUPPORTED; }
-teno_status teno_run_record(teno_ctx *, void *, int32_t, double, int32_t, void *, uint32_t *, double *) { return TENO_E_UNSUPPORTED; }
-teno_status teno_run_replay(teno_ctx *, void *, int32_t, const uint32_t *, const double *) { return TENO_E_UNSUPPORTED; }
-teno_status teno_run_vjp(teno_ctx *, const void *, const uint32_t *, const double *, int32_t, int32_t, void *) { return TENO_E_UNSUPPORTED; }
 teno_status teno_batch_create(const teno_grid *, int32_t, const teno_opts *, void *, teno_batch **) { return TENO_E_UNSUPPORTED; }
 teno_status teno_batch_destroy(teno_batch *) { return TENO_E_UNSUPPORTED; }
 size_t teno_batch_total_elems(const teno_batch *) { return 0; }

@@ -63,6 +63,7 @@ _SIGS = {
     "teno_run": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.c_double, ctypes.c_int32]),
     "teno_poll": (ctypes.c_int, [_P]),
     "teno_last_dt": (ctypes.c_int, [_P, _P]),
+    "teno_last_alpha": (ctypes.c_int, [_P, _P]),
     "teno_set_timing": (ctypes.c_int, [_P, ctypes.c_int32]),
     "teno_read_timing": (ctypes.c_int, [_P, _P, _P]),
     "teno_rhs_vjp": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
@@ -221,6 +222,12 @@ class Solver:
         _check(lib().teno_last_dt(self._h, ctypes.byref(v)), "teno_last_dt")
         return v.value
 
+    def last_alpha(self):
+        """The eight Lax-Friedrichs constants of the most recent evaluation (device tensor)."""
+        out = torch.empty(8, dtype=torch.float64, device="cuda")
+        _check(lib().teno_last_alpha(self._h, _ptr(out)), "teno_last_alpha")
+        return out
+
     def set_timing(self, enable=True):
         _check(lib().teno_set_timing(self._h, 1 if enable else 0), "teno_set_timing")
 
@@ -263,6 +270,51 @@ class Solver:
         _check(lib().teno_run_vjp(self._h, _ptr(rec["ckpt"]), _ptr(rec["masks"]), _ptr(rec["alpha_dt"]),
                                   int(rec["nsteps"]), int(rec["ckpt_every"]), _ptr(self._state(lam))), "teno_run_vjp")
         return lam
+
+
+class TenoRHS(torch.autograd.Function):
+    """dU/dt = L(U) with a backward pass through the frozen-selection adjoint (the stencil
+    selection and Lax-Friedrichs constants of the forward evaluation held fixed)."""
+
+    @staticmethod
+    def forward(ctx, U, solver):
+        masks = solver.masks_buffer()
+        out = solver.rhs(U.detach().contiguous(), masks=masks)
+        ctx.solver, ctx.masks, ctx.alpha = solver, masks, solver.last_alpha()
+        ctx.save_for_backward(U)
+        return out
+
+    @staticmethod
+    def backward(ctx, gout):
+        (U,) = ctx.saved_tensors
+        g = ctx.solver.rhs_vjp(U.detach().contiguous(), ctx.masks, ctx.alpha, gout.contiguous())
+        return g, None
+
+
+class TenoTrajectory(torch.autograd.Function):
+    """U(T) after nsteps SSP-RK3 steps from U0, differentiable through the frozen-selection adjoint
+    with checkpoints every ckpt_every steps (the backward pass recomputes one segment at a time)."""
+
+    @staticmethod
+    def forward(ctx, U0, solver, nsteps, ckpt_every, dt=0.0):
+        U = U0.detach().clone().contiguous()
+        rec = solver.run_record(U, nsteps, ckpt_every, dt=dt)
+        ctx.solver, ctx.rec = solver, rec
+        return U
+
+    @staticmethod
+    def backward(ctx, gout):
+        lam = gout.detach().clone().contiguous()
+        ctx.solver.run_vjp(ctx.rec, lam)
+        return lam, None, None, None, None
+
+
+def rhs(U, solver):
+    return TenoRHS.apply(U, solver)
+
+
+def trajectory(U0, solver, nsteps, ckpt_every=20, dt=0.0):
+    return TenoTrajectory.apply(U0, solver, nsteps, ckpt_every, dt)
 
 
 class Batch:
