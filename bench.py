@@ -90,6 +90,98 @@ def cpu_baseline(problem, budget_s=12.0):
                       f"of the {problem.nx}x{problem.ny} state, {t:.1f} s"}
 
 
+def batched_speedup(seed=3, nsteps=20):
+    """512 Euler instances (256 1D, N log-uniform in [256, 65536]; 256 2D squares, side log-uniform in
+    [64, 1024]) advanced nsteps SSP-RK3 steps: one persistent graph-captured launch sequence (mode 0,
+    autotuned tiles) vs one launch per instance per kernel (mode 1); states must be bitwise equal."""
+    import torch
+    from paper_1808_00037_amd import teno as T
+    from paper_1808_00037_amd import workloads as W
+
+    probs = W.batch(seed, nsteps=nsteps)
+    b = T.Batch(probs)
+    buf0 = b.pack([torch.from_numpy(p.U0) for p in probs])
+    cells = sum(p.ncells for p in probs)
+    # mode 0 first call tunes the launch shape and captures the graph
+    warm = buf0.clone()
+    b.run(warm, nsteps, mode=0)
+    b.run(warm.copy_(buf0), nsteps, mode=1)
+    torch.cuda.synchronize()
+    b.poll()
+    res = {}
+    outs = {}
+    for mode in (0, 1):
+        U = buf0.clone()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.run(U, nsteps, mode=mode)
+        e1.record()
+        torch.cuda.synchronize()
+        res[mode] = e0.elapsed_time(e1)
+        outs[mode] = U
+    b.poll()
+    equal = bool(torch.equal(outs[0], outs[1]))
+    b.close()
+    return {"instances": len(probs), "cells": cells, "steps": nsteps, "ms_batched": res[0], "ms_per_instance": res[1],
+            "speedup": res[1] / res[0], "bitwise_equal": equal,
+            "batched_Gcell_updates_per_s": cells * 3 * nsteps / (res[0] / 1e3) / 1e9}
+
+
+def adjoint_cost(n=1024, nsteps=400, ckpt=20, seed=21):
+    """Frozen-selection adjoint of 2D Euler n x n, nsteps steps, checkpoints every ckpt steps:
+    backward (segment recomputation + reverse sweep) time over the plain forward run time."""
+    import torch
+    from paper_1808_00037_amd import teno as T
+    from paper_1808_00037_amd import workloads as W
+
+    pr = W.euler2d(seed, n=n)
+    sv = T.Solver.for_problem(pr)
+    U0 = torch.from_numpy(pr.U0).cuda()
+    target = torch.from_numpy(W.density_target(seed, n)).cuda()
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
+
+    U = U0.clone()
+    sv.run(U, 2, graph=True)          # warm-up (graph capture)
+    U = U0.clone()
+    t_fwd = timed(lambda: sv.run(U, nsteps, graph=True))
+    U = U0.clone()
+    box = {}
+    t_rec = timed(lambda: box.setdefault("rec", sv.run_record(U, nsteps, ckpt)))
+    rec = box["rec"]
+    area = pr.dx * pr.dy
+    J = torch.sqrt(torch.sum((U[0] - target) ** 2) * area)
+    lam = torch.zeros_like(U)
+    lam[0] = (U[0] - target) * area / J
+    t_bwd = timed(lambda: sv.run_vjp(rec, lam))
+    sv.poll()
+    # central differences of the frozen map in a few seeded directions (the full 32-direction check
+    # is a GPU test)
+    worst = 0.0
+    for k, dn in enumerate(W.random_directions(77, pr.U0, 2)):
+        d = torch.from_numpy(dn).cuda()
+        h = 1e-6 * U0.abs().max() / d.abs().max()
+        Up, Um = U0 + h * d, U0 - h * d
+        sv.run_replay(Up, rec)
+        sv.run_replay(Um, rec)
+        Jp = torch.sqrt(torch.sum((Up[0] - target) ** 2) * area)
+        Jm = torch.sqrt(torch.sum((Um[0] - target) ** 2) * area)
+        fd = float((Jp - Jm) / (2 * h))
+        an = float(torch.sum(lam * d))
+        worst = max(worst, abs(fd - an) / abs(an))
+    sv.poll()
+    return {"n": n, "steps": nsteps, "ckpt_every": ckpt, "ms_forward": t_fwd, "ms_record": t_rec,
+            "ms_backward": t_bwd, "bwd_over_fwd": t_bwd / t_fwd, "fd_rel_err_2dirs": worst}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -168,6 +260,15 @@ def main():
 
     del sv, U
     torch.cuda.empty_cache()
+    if not args.no_extras:
+        log("batched vs one launch per instance (512 instances)")
+        out["batched"] = batched_speedup()
+        log(json.dumps(out["batched"]))
+        torch.cuda.empty_cache()
+        log("adjoint cost (1024^2, 400 steps, checkpoints every 20)")
+        out["adjoint"] = adjoint_cost()
+        log(json.dumps(out["adjoint"]))
+        torch.cuda.empty_cache()
     if not args.no_cpu:
         log("oracle CPU baseline")
         out["cpu_baseline"] = cpu_baseline(pr)

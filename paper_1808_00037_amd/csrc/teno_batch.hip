@@ -1,0 +1,553 @@
+// teno_batch.hip -- many independent Euler problems (1D and 2D, uneven sizes) advanced together.
+//
+// All instances live in one packed state buffer (and packed RK-stage scratch). Each sweep of a
+// stage is one persistent launch over a static work list of (instance, tile) items: block b takes
+// items b, b + G, b + 2G, ... (instance-major order, so concurrently running blocks share an
+// instance's rows in L2). Every instance keeps its own Lax-Friedrichs constants, CFL dt and spread
+// wave-speed maxima. Mode 0 captures the whole nsteps run (per step: 3 x [stage prep, y-sweep of
+// the 2D instances, x-sweep + stage update of all]) in one HIP graph and launches it once; mode 1
+// launches the same kernels once per instance per kernel on the stream. A face or cell is computed
+// by the same code whatever tile or launch holds it, so both modes give bitwise identical states.
+//
+// Tile shapes (segments per x-tile, columns per y-tile) and the persistent grid size are picked by
+// a small autotuner at the first mode-0 run: each candidate advances a scratch copy of the batch by
+// one step (after a warm-up step) and the fastest is kept for the batch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "teno.h"
+#include "teno_device.hpp"
+
+using namespace teno;
+
+#define HIP_TRY(expr)                                   \
+    do {                                                \
+        hipError_t e_ = (expr);                         \
+        if (e_ != hipSuccess) return TENO_E_HIP;        \
+    } while (0)
+
+namespace {
+
+constexpr int NCOPY_B = 8;          // spread copies of the maxima per instance
+constexpr int WS_CHUNK = 8192;      // cells per wave-speed work item
+
+struct BatchInst {
+    int sys, nx, ny, bc_x, bc_y;
+    int pad_;
+    long long off;                  // element offset of the instance in the packed buffers
+    double inv_dx, inv_dy, eps_x, eps_y;
+};
+
+struct InstCtrl {
+    unsigned long long part[3][NCOPY_B][NWORD];
+    double alpha[8];
+    double den, dt;
+};
+
+struct Item {
+    int inst, tile;
+};
+
+template <typename T> struct BatchSweep {
+    const BatchInst *inst;
+    InstCtrl *ictrl;
+    const Item *items;
+    int begin, end;                 // item range of this launch
+    const T *U;                     // stage input (packed)
+    const T *U0;                    // RK base state (packed)
+    const T *addend;                // y-part of dU/dt (packed, 2D instances only)
+    T *out;                         // dU/dt (y) or the next stage (x)
+    unsigned *err;
+    int mode, stage, ring_next, scheme, alpha_mode;
+    T ct, gamma;
+};
+
+int nseg_of(int len) { return (len + SEG_CELLS - 1) / SEG_CELLS; }
+
+int tiles_x(const teno_grid &g, int nseg_x)
+{
+    long long segs = (long long)nseg_of(g.nx) * g.ny;
+    return (int)((segs + nseg_x - 1) / nseg_x);
+}
+
+int tiles_y(const teno_grid &g, int nseg_y)
+{
+    return ((g.nx + nseg_y - 1) / nseg_y) * nseg_of(g.ny);
+}
+
+}  // namespace
+
+// per-item arguments of the plain sweep code
+template <typename T, int DIR>
+__device__ __forceinline__ SweepArgs<T> item_args(const BatchSweep<T> &b, const BatchInst &I, int k)
+{
+    SweepArgs<T> a;
+    a.U = b.U + I.off;
+    a.U0 = b.U0 ? b.U0 + I.off : nullptr;
+    a.addend = (b.addend && I.sys == EULER2D) ? b.addend + I.off : nullptr;
+    a.out = b.out + I.off;
+    a.Fout = nullptr;
+    a.masks_out = nullptr;
+    a.flags_out = nullptr;
+    a.masks_in = nullptr;
+    a.alpha = b.ictrl[k].alpha;
+    a.dt = &b.ictrl[k].dt;
+    a.part = nullptr;
+    a.err = b.err;
+    a.nx = I.nx;
+    a.ny = I.ny;
+    a.len = DIR == 0 ? I.nx : I.ny;
+    a.nlines = DIR == 0 ? I.ny : I.nx;
+    a.nseg = (a.len + SEG_CELLS - 1) / SEG_CELLS;
+    a.bc = DIR == 0 ? I.bc_x : I.bc_y;
+    a.bc_other = 0;
+    a.mode = b.mode;
+    a.stage = b.stage;
+    a.scheme = b.scheme;
+    a.alpha_mode = b.alpha_mode;
+    a.inv_h = (T)(DIR == 0 ? I.inv_dx : I.inv_dy);
+    a.eps = (T)(DIR == 0 ? I.eps_x : I.eps_y);
+    a.ct = b.ct;
+    a.gamma = b.gamma;
+    a.adv = T(1);
+    a.inv_dx = (T)I.inv_dx;
+    a.inv_dy = (T)I.inv_dy;
+    return a;
+}
+
+template <typename T, int DIR, int NSEG>
+__global__ void __launch_bounds__(BLOCK, 3) batch_sweep_kernel(BatchSweep<T> b)
+{
+    __shared__ T rec[NSEG * seg_stride<EULER2D>()];
+    __shared__ T coef[NCOEF_ROWS * 8];
+    __shared__ double red[BLOCK / WAVE * 9];
+    fill_coef(coef);
+    for (int it = b.begin + (int)blockIdx.x; it < b.end; it += (int)gridDim.x) {
+        const Item item = b.items[it];
+        const BatchInst I = b.inst[item.inst];
+        SweepArgs<T> a = item_args<T, DIR>(b, I, item.inst);
+        unsigned long long *copy =
+            b.mode == MODE_STAGE ? &b.ictrl[item.inst].part[b.ring_next][item.tile % NCOPY_B][0] : nullptr;
+        if (I.sys == EULER2D) sweep_tile<T, EULER2D, DIR, false, NSEG>(a, item.tile, rec, coef, red, copy);
+        else if (DIR == 0) sweep_tile<T, EULER1D, 0, false, NSEG>(a, item.tile, rec, coef, red, copy);
+        __syncthreads();              // the next item restages the LDS tile
+    }
+}
+
+// Wave-speed maxima of every instance of a packed state (items: (instance, chunk of WS_CHUNK cells)).
+template <typename T>
+__global__ void __launch_bounds__(BLOCK) batch_wavespeed_kernel(const T *U, const BatchInst *inst, InstCtrl *ictrl,
+                                                                const Item *items, int begin, int end, T gamma,
+                                                                int alpha_mode, int ring, unsigned *err)
+{
+    __shared__ double red[BLOCK / WAVE * 9];
+    for (int it = begin + (int)blockIdx.x; it < end; it += (int)gridDim.x) {
+        const Item item = items[it];
+        const BatchInst I = inst[item.inst];
+        const size_t ncell = (size_t)I.nx * I.ny;
+        const size_t c0 = (size_t)item.tile * WS_CHUNK;
+        const size_t c1 = c0 + WS_CHUNK < ncell ? c0 + WS_CHUNK : ncell;
+        double wmax[9];
+        for (int k = 0; k < 9; ++k) wmax[k] = 0.0;
+        unsigned bad = 0;
+        for (size_t i = c0 + threadIdx.x; i < c1; i += BLOCK) {
+            T u[4];
+            const int nv = I.sys == EULER2D ? 4 : 3;
+            for (int v = 0; v < nv; ++v) u[v] = U[I.off + (size_t)v * ncell + i];
+            double w[9];
+            bool ok = I.sys == EULER2D
+                          ? cell_speeds<T, EULER2D>(u, gamma, T(1), (T)I.inv_dx, (T)I.inv_dy, alpha_mode, w)
+                          : cell_speeds<T, EULER1D>(u, gamma, T(1), (T)I.inv_dx, (T)I.inv_dy, alpha_mode, w);
+            if (!ok) bad |= ERR_NONPHYSICAL;
+            for (int k = 0; k < 9; ++k) wmax[k] = fmax(wmax[k], w[k]);
+        }
+        block_max_atomic(wmax, &ictrl[item.inst].part[ring][item.tile % NCOPY_B][0], red);
+        if (bad) atomicOr(err, bad);
+        __syncthreads();
+    }
+}
+
+// Per-instance stage preparation (the batched form of prep_kernel): reduce the spread maxima of
+// one ring slot into alpha/den (and dt at stage 0), then clear the slot. One block per instance.
+__global__ void batch_prep_kernel(InstCtrl *ictrl, int first, int count, int ring, int stage, double cfl,
+                                  unsigned *err)
+{
+    for (int k = first + (int)blockIdx.x; k < first + count; k += (int)gridDim.x) {
+        __shared__ double vals[NWORD];
+        InstCtrl &C = ictrl[k];
+        const int t = threadIdx.x;
+        if (t < 9) {
+            unsigned long long m = 0;
+            for (int c = 0; c < NCOPY_B; ++c) {
+                unsigned long long v = C.part[ring][c][t];
+                m = v > m ? v : m;
+            }
+            vals[t] = __longlong_as_double((long long)m);
+        }
+        __syncthreads();
+        for (int q = t; q < NCOPY_B * NWORD; q += blockDim.x) (&C.part[ring][0][0])[q] = 0ull;
+        if (t < 8) C.alpha[t] = vals[t];
+        if (t == 8) {
+            C.den = vals[8];
+            if (stage == 0) {
+                double dt = cfl / vals[8];
+                if (!(dt > 0.0) || !isfinite(dt)) atomicOr(err, ERR_NONFINITE);
+                C.dt = dt;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void batch_clear_kernel(InstCtrl *ictrl, int n, int ring)
+{
+    for (int k = blockIdx.x; k < n; k += gridDim.x)
+        for (int q = threadIdx.x; q < NCOPY_B * NWORD; q += blockDim.x) (&ictrl[k].part[ring][0][0])[q] = 0ull;
+}
+
+struct teno_batch {
+    int n = 0;
+    teno_opts opts;
+    hipStream_t stream = nullptr;
+    int dtype = TENO_F64;
+    size_t esize = 8, total = 0;
+    std::vector<teno_grid> grids;
+    std::vector<BatchInst> inst;
+    BatchInst *inst_d = nullptr;
+    InstCtrl *ictrl_d = nullptr;
+    unsigned *err_d = nullptr;
+    void *S1 = nullptr, *S2 = nullptr, *dUy = nullptr;
+    // work lists, one per tile-shape variant (index 0: 4 segments, 1: 8 segments per tile)
+    Item *items_x_d[2] = {nullptr, nullptr}, *items_y_d[2] = {nullptr, nullptr};
+    std::vector<int> begin_x[2], begin_y[2];          // per-instance item ranges (n + 1 entries)
+    Item *items_w_d = nullptr;
+    std::vector<int> begin_w;
+    // tuned launch shape
+    bool tuned = false;
+    int vx = 0, vy = 1, blocks_per_cu = 3;
+    int num_cu = 256;
+    // captured run
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    void *graph_U = nullptr;
+    int graph_steps = -1;
+};
+
+namespace {
+
+template <typename T>
+BatchSweep<T> base_args(const teno_batch *b)
+{
+    BatchSweep<T> a;
+    std::memset(&a, 0, sizeof a);
+    a.inst = b->inst_d;
+    a.ictrl = b->ictrl_d;
+    a.err = b->err_d;
+    a.scheme = b->opts.scheme;
+    a.alpha_mode = b->opts.alpha_mode;
+    a.ct = (T)b->opts.ct;
+    a.gamma = (T)b->opts.gamma;
+    return a;
+}
+
+template <typename T, int DIR>
+void launch_batch_sweep(teno_batch *b, hipStream_t s, int variant, BatchSweep<T> a, int grid)
+{
+    if (a.end <= a.begin) return;
+    if (variant == 0)
+        hipLaunchKernelGGL((batch_sweep_kernel<T, DIR, 4>), dim3(grid), dim3(BLOCK), 0, s, a);
+    else
+        hipLaunchKernelGGL((batch_sweep_kernel<T, DIR, 8>), dim3(grid), dim3(BLOCK), 0, s, a);
+}
+
+int persistent_grid(const teno_batch *b, int nitems)
+{
+    int g = b->num_cu * b->blocks_per_cu;
+    return nitems < g ? (nitems > 0 ? nitems : 1) : g;
+}
+
+// Enqueue one SSP-RK3 step of the instances [first, last) (mode 0: all in one launch per kernel).
+template <typename T>
+void enqueue_step_range(teno_batch *b, hipStream_t s, T *U, int first, int last, bool per_instance_grid,
+                        int vx, int vy)
+{
+    T *in[3] = {U, (T *)b->S1, (T *)b->S2};
+    T *outp[3] = {(T *)b->S1, (T *)b->S2, U};
+    for (int k = 0; k < 3; ++k) {
+        const int cnt = last - first;
+        hipLaunchKernelGGL(batch_prep_kernel, dim3(cnt < 1024 ? cnt : 1024), dim3(64), 0, s, b->ictrl_d, first, cnt,
+                           k, k, b->opts.cfl, b->err_d);
+        BatchSweep<T> a = base_args<T>(b);
+        a.stage = k;
+        a.U = in[k];
+        a.items = b->items_y_d[vy];
+        a.begin = b->begin_y[vy][first];
+        a.end = b->begin_y[vy][last];
+        a.mode = MODE_RHS;
+        a.out = (T *)b->dUy;
+        int ny_items = a.end - a.begin;
+        launch_batch_sweep<T, 1>(b, s, vy, a, per_instance_grid ? (ny_items > 0 ? ny_items : 1)
+                                                                : persistent_grid(b, ny_items));
+        a.items = b->items_x_d[vx];
+        a.begin = b->begin_x[vx][first];
+        a.end = b->begin_x[vx][last];
+        a.mode = MODE_STAGE;
+        a.U0 = U;
+        a.addend = (T *)b->dUy;
+        a.out = outp[k];
+        a.ring_next = (k + 1) % 3;
+        int nx_items = a.end - a.begin;
+        launch_batch_sweep<T, 0>(b, s, vx, a, per_instance_grid ? nx_items : persistent_grid(b, nx_items));
+    }
+}
+
+template <typename T>
+void enqueue_init(teno_batch *b, hipStream_t s, const T *U, int first, int last)
+{
+    hipLaunchKernelGGL(batch_clear_kernel, dim3(256), dim3(256), 0, s, b->ictrl_d, b->n, 0);
+    int beg = b->begin_w[first], end = b->begin_w[last];
+    int grid = end - beg < 4096 ? end - beg : 4096;
+    if (grid > 0)
+        hipLaunchKernelGGL((batch_wavespeed_kernel<T>), dim3(grid), dim3(BLOCK), 0, s, U, b->inst_d, b->ictrl_d,
+                           b->items_w_d, beg, end, (T)b->opts.gamma, b->opts.alpha_mode, 0, b->err_d);
+}
+
+template <typename T>
+teno_status run_t(teno_batch *b, T *U, int nsteps, int mode)
+{
+    if (mode == 1) {
+        // one launch per instance per kernel, plain stream launches
+        enqueue_init<T>(b, b->stream, U, 0, b->n);
+        for (int n = 0; n < nsteps; ++n)
+            for (int k = 0; k < b->n; ++k) enqueue_step_range<T>(b, b->stream, U, k, k + 1, true, 0, 1);
+        return hipGetLastError() == hipSuccess ? TENO_OK : TENO_E_HIP;
+    }
+    if (!b->tuned) {
+        // autotune on a scratch copy of the batch: candidates (x-tile, y-tile, blocks per CU)
+        T *tmp = nullptr;
+        HIP_TRY(hipMalloc(&tmp, b->total * sizeof(T)));
+        HIP_TRY(hipMemcpyAsync(tmp, U, b->total * sizeof(T), hipMemcpyDeviceToDevice, b->stream));
+        hipEvent_t e0, e1;
+        HIP_TRY(hipEventCreate(&e0));
+        HIP_TRY(hipEventCreate(&e1));
+        float best = 1e30f;
+        int bvx = 0, bvy = 1, bbpc = 3;
+        const int bpcs[3] = {2, 3, 4};
+        for (int vx = 0; vx < 2; ++vx)
+            for (int vy = 0; vy < 2; ++vy)
+                for (int bi = 0; bi < 3; ++bi) {
+                    b->blocks_per_cu = bpcs[bi];
+                    enqueue_init<T>(b, b->stream, tmp, 0, b->n);
+                    enqueue_step_range<T>(b, b->stream, tmp, 0, b->n, false, vx, vy);    // warm-up
+                    HIP_TRY(hipEventRecord(e0, b->stream));
+                    enqueue_step_range<T>(b, b->stream, tmp, 0, b->n, false, vx, vy);
+                    HIP_TRY(hipEventRecord(e1, b->stream));
+                    HIP_TRY(hipEventSynchronize(e1));
+                    float ms = 0.f;
+                    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+                    if (ms < best) { best = ms; bvx = vx; bvy = vy; bbpc = bpcs[bi]; }
+                }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        HIP_TRY(hipFree(tmp));
+        b->vx = bvx;
+        b->vy = bvy;
+        b->blocks_per_cu = bbpc;
+        b->tuned = true;
+        unsigned z = 0;     // the tuning run's state is discarded, and so is its status
+        HIP_TRY(hipMemcpy(b->err_d, &z, sizeof z, hipMemcpyHostToDevice));
+    }
+    if (!b->exec || b->graph_U != (void *)U || b->graph_steps != nsteps) {
+        if (b->exec) (void)hipGraphExecDestroy(b->exec);
+        if (b->graph) (void)hipGraphDestroy(b->graph);
+        b->exec = nullptr;
+        b->graph = nullptr;
+        if (!b->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+        HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+        enqueue_init<T>(b, b->cap_stream, U, 0, b->n);
+        for (int n = 0; n < nsteps; ++n) enqueue_step_range<T>(b, b->cap_stream, U, 0, b->n, false, b->vx, b->vy);
+        HIP_TRY(hipStreamEndCapture(b->cap_stream, &b->graph));
+        HIP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+        b->graph_U = U;
+        b->graph_steps = nsteps;
+    }
+    HIP_TRY(hipGraphLaunch(b->exec, b->stream));
+    return TENO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+teno_status teno_batch_create(const teno_grid *grids, int32_t n, const teno_opts *opts, void *stream, teno_batch **out)
+{
+    if (!out || !grids || !opts || n < 1) return TENO_E_ARG;
+    *out = nullptr;
+    const int dtype = grids[0].dtype;
+    for (int k = 0; k < n; ++k) {
+        const teno_grid &g = grids[k];
+        if (g.sys != TENO_EULER1D && g.sys != TENO_EULER2D) return TENO_E_UNSUPPORTED;
+        if (g.dtype != dtype || g.dtype < 0 || g.dtype > 1) return TENO_E_ARG;
+        if (g.nx < 1 || g.ny < 1 || g.nx > (1 << 20) || g.ny > (1 << 20)) return TENO_E_ARG;
+        if (g.sys == TENO_EULER1D && g.ny != 1) return TENO_E_ARG;
+        if (g.bc_x < 0 || g.bc_x > 1 || g.bc_y < 0 || g.bc_y > 1) return TENO_E_ARG;
+        if (!(g.x1 > g.x0) || !(g.y1 > g.y0)) return TENO_E_ARG;
+    }
+    if (opts->scheme < 0 || opts->scheme > 1 || opts->alpha_mode < 0 || opts->alpha_mode > 1) return TENO_E_ARG;
+    if (!(opts->gamma > 1.0) || !(opts->ct > 0.0 && opts->ct < 1.0 / 3.0) || !(opts->cfl > 0.0)) return TENO_E_ARG;
+    if (opts->eps_mode == 1 && !(opts->eps > 0.0)) return TENO_E_ARG;
+
+    teno_batch *b = new (std::nothrow) teno_batch();
+    if (!b) return TENO_E_HIP;
+    b->n = n;
+    b->opts = *opts;
+    b->stream = (hipStream_t)stream;
+    b->dtype = dtype;
+    b->esize = dtype == TENO_F64 ? 8 : 4;
+    b->grids.assign(grids, grids + n);
+    size_t off = 0;
+    for (int k = 0; k < n; ++k) {
+        const teno_grid &g = grids[k];
+        BatchInst I;
+        std::memset(&I, 0, sizeof I);
+        I.sys = g.sys;
+        I.nx = g.nx;
+        I.ny = g.ny;
+        I.bc_x = g.bc_x;
+        I.bc_y = g.bc_y;
+        I.off = (long long)off;
+        double dx = (g.x1 - g.x0) / g.nx, dy = (g.y1 - g.y0) / g.ny;
+        I.inv_dx = 1.0 / dx;
+        I.inv_dy = 1.0 / dy;
+        if (opts->eps_mode == 1) I.eps_x = I.eps_y = opts->eps;
+        else if (opts->scheme == TENO_SCHEME_TENO5) I.eps_x = I.eps_y = 1e-40;
+        else { I.eps_x = dx * dx * dx; I.eps_y = dy * dy * dy; }
+        b->inst.push_back(I);
+        size_t ne = (size_t)(g.sys == TENO_EULER2D ? 4 : 3) * g.nx * g.ny;
+        off += (ne + 63) / 64 * 64;                       // 512-byte aligned instances (FP64)
+    }
+    b->total = off;
+    int dev = 0;
+    teno_status st = TENO_OK;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        int cu = 0;
+        if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cu > 0)
+            b->num_cu = cu;
+    }
+    // work lists
+    std::vector<Item> it;
+    for (int v = 0; v < 2; ++v) {
+        const int ns = v == 0 ? 4 : 8;
+        it.clear();
+        b->begin_x[v].assign(1, 0);
+        for (int k = 0; k < n; ++k) {
+            int t = tiles_x(grids[k], ns);
+            for (int q = 0; q < t; ++q) it.push_back({k, q});
+            b->begin_x[v].push_back((int)it.size());
+        }
+        if (hipMalloc(&b->items_x_d[v], it.size() * sizeof(Item)) != hipSuccess ||
+            hipMemcpy(b->items_x_d[v], it.data(), it.size() * sizeof(Item), hipMemcpyHostToDevice) != hipSuccess)
+            st = TENO_E_HIP;
+        it.clear();
+        b->begin_y[v].assign(1, 0);
+        for (int k = 0; k < n; ++k) {
+            if (grids[k].sys == TENO_EULER2D) {
+                int t = tiles_y(grids[k], ns);
+                for (int q = 0; q < t; ++q) it.push_back({k, q});
+            }
+            b->begin_y[v].push_back((int)it.size());
+        }
+        if (hipMalloc(&b->items_y_d[v], (it.size() + 1) * sizeof(Item)) != hipSuccess ||
+            (it.size() && hipMemcpy(b->items_y_d[v], it.data(), it.size() * sizeof(Item), hipMemcpyHostToDevice) !=
+                              hipSuccess))
+            st = TENO_E_HIP;
+    }
+    it.clear();
+    b->begin_w.assign(1, 0);
+    for (int k = 0; k < n; ++k) {
+        size_t nc = (size_t)grids[k].nx * grids[k].ny;
+        int t = (int)((nc + WS_CHUNK - 1) / WS_CHUNK);
+        for (int q = 0; q < t; ++q) it.push_back({k, q});
+        b->begin_w.push_back((int)it.size());
+    }
+    if (hipMalloc(&b->items_w_d, it.size() * sizeof(Item)) != hipSuccess ||
+        hipMemcpy(b->items_w_d, it.data(), it.size() * sizeof(Item), hipMemcpyHostToDevice) != hipSuccess)
+        st = TENO_E_HIP;
+    if (hipMalloc(&b->inst_d, n * sizeof(BatchInst)) != hipSuccess ||
+        hipMemcpy(b->inst_d, b->inst.data(), n * sizeof(BatchInst), hipMemcpyHostToDevice) != hipSuccess)
+        st = TENO_E_HIP;
+    if (hipMalloc(&b->ictrl_d, n * sizeof(InstCtrl)) != hipSuccess ||
+        hipMemset(b->ictrl_d, 0, n * sizeof(InstCtrl)) != hipSuccess)
+        st = TENO_E_HIP;
+    if (hipMalloc(&b->err_d, sizeof(unsigned)) != hipSuccess || hipMemset(b->err_d, 0, sizeof(unsigned)) != hipSuccess)
+        st = TENO_E_HIP;
+    if (hipMalloc(&b->S1, b->total * b->esize) != hipSuccess || hipMalloc(&b->S2, b->total * b->esize) != hipSuccess ||
+        hipMalloc(&b->dUy, b->total * b->esize) != hipSuccess)
+        st = TENO_E_HIP;
+    if (st != TENO_OK) {
+        teno_batch_destroy(b);
+        return st;
+    }
+    *out = b;
+    return TENO_OK;
+}
+
+teno_status teno_batch_destroy(teno_batch *b)
+{
+    if (!b) return TENO_E_ARG;
+    (void)hipStreamSynchronize(b->stream);
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+    for (int v = 0; v < 2; ++v) {
+        (void)hipFree(b->items_x_d[v]);
+        (void)hipFree(b->items_y_d[v]);
+    }
+    (void)hipFree(b->items_w_d);
+    (void)hipFree(b->inst_d);
+    (void)hipFree(b->ictrl_d);
+    (void)hipFree(b->err_d);
+    (void)hipFree(b->S1);
+    (void)hipFree(b->S2);
+    (void)hipFree(b->dUy);
+    delete b;
+    return TENO_OK;
+}
+
+size_t teno_batch_total_elems(const teno_batch *b) { return b ? b->total : 0; }
+
+size_t teno_batch_offset(const teno_batch *b, int32_t k)
+{
+    if (!b || k < 0 || k >= b->n) return (size_t)-1;
+    return (size_t)b->inst[k].off;
+}
+
+teno_status teno_batch_run(teno_batch *b, void *U_dev, int32_t nsteps, int32_t mode)
+{
+    if (!b || !U_dev || nsteps < 0 || mode < 0 || mode > 1) return TENO_E_ARG;
+    if (b->dtype == TENO_F64) return run_t<double>(b, (double *)U_dev, nsteps, mode);
+    return run_t<float>(b, (float *)U_dev, nsteps, mode);
+}
+
+teno_status teno_batch_poll(teno_batch *b)
+{
+    if (!b) return TENO_E_ARG;
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    unsigned e = 0;
+    HIP_TRY(hipMemcpy(&e, b->err_d, sizeof e, hipMemcpyDeviceToHost));
+    if (e) {
+        unsigned z = 0;
+        HIP_TRY(hipMemcpy(b->err_d, &z, sizeof z, hipMemcpyHostToDevice));
+    }
+    if (e & ERR_NONFINITE) return TENO_E_NONFINITE;
+    if (e & ERR_NONPHYSICAL) return TENO_E_NONPHYSICAL;
+    if (e & ERR_SELECTION) return TENO_E_NONFINITE;
+    return TENO_OK;
+}
+
+}  // extern "C"

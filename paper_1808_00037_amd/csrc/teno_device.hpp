@@ -370,8 +370,8 @@ __device__ __forceinline__ double wave_max(double v)
     return v;
 }
 
-// Block-wide maxima of nine per-lane values -> one atomicMax per word into a spread copy.
-__device__ __forceinline__ void block_max_atomic(double w[9], unsigned long long *part, double *lds9)
+// Block-wide maxima of nine per-lane values -> one atomicMax per word into one spread copy.
+__device__ __forceinline__ void block_max_atomic(double w[9], unsigned long long *copy, double *lds9)
 {
     const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
 #pragma unroll
@@ -382,8 +382,7 @@ __device__ __forceinline__ void block_max_atomic(double w[9], unsigned long long
     if (threadIdx.x < 9) {
         double m = 0.0;
         for (int q = 0; q < BLOCK / WAVE; ++q) m = fmax(m, lds9[q * 9 + threadIdx.x]);
-        unsigned long long *dst = part + (size_t)(blockIdx.x % NCOPY) * NWORD + threadIdx.x;
-        atomicMax(dst, (unsigned long long)__double_as_longlong(m));
+        atomicMax(copy + threadIdx.x, (unsigned long long)__double_as_longlong(m));
     }
 }
 
@@ -402,38 +401,44 @@ __device__ __forceinline__ void block_max_atomic(double w[9], unsigned long long
 #define TENO_MIN_WAVES_Y 3
 #endif
 
-template <typename T, int SYS, int DIR, bool FROZEN>
-__global__ void __launch_bounds__(BLOCK, DIR == 0 ? TENO_MIN_WAVES_X : TENO_MIN_WAVES_Y) sweep_kernel(SweepArgs<T> a)
+// LDS record stride of one staged segment (odd: the y staging stores spread over the banks).
+template <int SYS> constexpr int seg_stride() { return Sys<SYS>::NREC * SEG_LOAD + 1; }
+
+// Fill the block's coefficient table (rows of Tables 2 and 1, correctly rounded in T).
+template <typename T> __device__ __forceinline__ void fill_coef(T *coef)
+{
+    for (int q = threadIdx.x; q < NCOEF_ROWS * 8; q += BLOCK) {
+        int r = q / 8, l = q % 8;
+        coef[q] = l < 7 ? T(COEF[r][l].n) / T(COEF[r][l].d) : T(0);
+    }
+}
+
+// One tile of a sweep: NSEG line segments staged together in LDS. `tile` enumerates the tiles of
+// the sweep (x: NSEG consecutive segments of the row-major segment list; y: NSEG adjacent columns
+// at one segment position). rec/coef/red: the block's LDS; `copy`: the spread copy of the wave-speed
+// maxima this tile accumulates into (MODE_STAGE).
+template <typename T, int SYS, int DIR, bool FROZEN, int NSEG>
+__device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *rec, const T *coef, double *red,
+                                           unsigned long long *part_copy)
 {
     constexpr int NV = Sys<SYS>::NV;
-    constexpr int NREC = Sys<SYS>::NREC;
-    constexpr int NSEG = DIR == 0 ? NSEG_X : NSEG_Y;
-    constexpr int SEG_STRIDE = NREC * SEG_LOAD + 1;   // odd stride: y staging stores spread banks
+    constexpr int SEG_STRIDE = seg_stride<SYS>();
     constexpr bool EULER = SYS == EULER1D || SYS == EULER2D;
-
-    __shared__ T rec[NSEG * SEG_STRIDE];
-    __shared__ T coef[NCOEF_ROWS * 8];
-    __shared__ double red[BLOCK / WAVE * 9];
 
     const int tid = threadIdx.x, lane = tid & (WAVE - 1), wid = tid / WAVE;
     const size_t ncell = (size_t)a.nx * a.ny;
 
-    for (int q = tid; q < NCOEF_ROWS * 8; q += BLOCK) {
-        int r = q / 8, l = q % 8;
-        coef[q] = l < 7 ? T(COEF[r][l].n) / T(COEF[r][l].d) : T(0);
-    }
-
     // segment s of this block -> (line, c0); line < 0 marks an empty slot
     auto seg_of = [&](int s, int &line, int &c0) {
         if (DIR == 0) {
-            int id = blockIdx.x * NSEG + s;
+            int id = tile * NSEG + s;
             line = id / a.nseg;
             c0 = (id % a.nseg) * SEG_CELLS;
             if (line >= a.nlines) line = -1;
         } else {
             int ntile = (a.nlines + NSEG - 1) / NSEG;
-            int pos = blockIdx.x / ntile;
-            line = (blockIdx.x % ntile) * NSEG + s;
+            int pos = tile / ntile;
+            line = (tile % ntile) * NSEG + s;
             c0 = pos * SEG_CELLS;
             if (line >= a.nlines) line = -1;
         }
@@ -697,8 +702,20 @@ __global__ void __launch_bounds__(BLOCK, DIR == 0 ? TENO_MIN_WAVES_X : TENO_MIN_
             }
         }
     }
-    if (a.mode == MODE_STAGE) block_max_atomic(wmax, a.part, red);
+    if (a.mode == MODE_STAGE) block_max_atomic(wmax, part_copy, red);
     if (bad) atomicOr(a.err, bad);
+}
+
+template <typename T, int SYS, int DIR, bool FROZEN>
+__global__ void __launch_bounds__(BLOCK, DIR == 0 ? TENO_MIN_WAVES_X : TENO_MIN_WAVES_Y) sweep_kernel(SweepArgs<T> a)
+{
+    constexpr int NSEG = DIR == 0 ? NSEG_X : NSEG_Y;
+    __shared__ T rec[NSEG * seg_stride<SYS>()];
+    __shared__ T coef[NCOEF_ROWS * 8];
+    __shared__ double red[BLOCK / WAVE * 9];
+    fill_coef(coef);
+    sweep_tile<T, SYS, DIR, FROZEN, NSEG>(a, blockIdx.x, rec, coef, red,
+                                          a.part ? a.part + (size_t)(blockIdx.x % NCOPY) * NWORD : nullptr);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -723,7 +740,7 @@ __global__ void __launch_bounds__(BLOCK) wavespeed_kernel(const T *U, size_t nce
 #pragma unroll
         for (int k = 0; k < 9; ++k) wmax[k] = fmax(wmax[k], w[k]);
     }
-    block_max_atomic(wmax, part, red);
+    block_max_atomic(wmax, part + (size_t)(blockIdx.x % NCOPY) * NWORD, red);
     if (bad) atomicOr(err, bad);
 }
 
