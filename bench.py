@@ -191,6 +191,9 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-extras", action="store_true", help="skip the batched and adjoint side runs")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="after the timed region, one plain device-to-device copy of this many bytes "
+                         "(a reference kernel for calibrating profiler byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -258,6 +261,13 @@ def main():
                    "achieved_GBps": value * BYTES_PER_CELL_UPDATE, "peak_GBps": PEAK_HBM / 1e9, "frac": hbm_frac},
            "kernels_ms": {"x_sweep_stage": x_ms, "y_sweep": y_ms}}
 
+    if args.copy_bytes > 0:
+        src = torch.ones(args.copy_bytes // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     del sv, U
     torch.cuda.empty_cache()
     if not args.no_extras:

@@ -113,28 +113,37 @@ __device__ __forceinline__ SweepArgs<T> item_args(const BatchSweep<T> &b, const 
     a.eps = (T)(DIR == 0 ? I.eps_x : I.eps_y);
     a.ct = b.ct;
     a.gamma = b.gamma;
+    a.gm1 = b.gamma - T(1);
     a.adv = T(1);
     a.inv_dx = (T)I.inv_dx;
     a.inv_dy = (T)I.inv_dy;
     return a;
 }
 
+// y-sweeps produce the y-part of dU/dt (MODE_RHS), x-sweeps apply the RK stage (MODE_STAGE).
 template <typename T, int DIR, int NSEG>
 __global__ void __launch_bounds__(BLOCK, 3) batch_sweep_kernel(BatchSweep<T> b)
 {
+    constexpr int MODE = DIR == 0 ? MODE_STAGE : MODE_RHS;
     __shared__ T rec[NSEG * seg_stride<EULER2D>()];
+    __shared__ T ext[ext_size<T, EULER2D, DIR, NSEG, MODE>()];
     __shared__ T coef[NCOEF_ROWS * 8];
     __shared__ double red[BLOCK / WAVE * 9];
     fill_coef(coef);
+    if (MODE == MODE_STAGE) clear_maxima(red);
     for (int it = b.begin + (int)blockIdx.x; it < b.end; it += (int)gridDim.x) {
         const Item item = b.items[it];
         const BatchInst I = b.inst[item.inst];
         SweepArgs<T> a = item_args<T, DIR>(b, I, item.inst);
-        unsigned long long *copy =
-            b.mode == MODE_STAGE ? &b.ictrl[item.inst].part[b.ring_next][item.tile % NCOPY_B][0] : nullptr;
-        if (I.sys == EULER2D) sweep_tile<T, EULER2D, DIR, false, NSEG>(a, item.tile, rec, coef, red, copy);
-        else if (DIR == 0) sweep_tile<T, EULER1D, 0, false, NSEG>(a, item.tile, rec, coef, red, copy);
+        if (I.sys == EULER2D) sweep_tile<T, EULER2D, DIR, false, NSEG, MODE>(a, item.tile, rec, ext, coef, red);
+        else if (DIR == 0) sweep_tile<T, EULER1D, 0, false, NSEG, MODE>(a, item.tile, rec, ext, coef, red);
         __syncthreads();              // the next item restages the LDS tile
+        if (MODE == MODE_STAGE) {
+            // flush the maxima when the block's next item belongs to another instance (or none)
+            const int nxt = it + (int)gridDim.x;
+            if (nxt >= b.end || b.items[nxt].inst != item.inst)
+                flush_maxima(red, &b.ictrl[item.inst].part[b.ring_next][blockIdx.x % NCOPY_B][0]);
+        }
     }
 }
 

@@ -38,7 +38,10 @@ constexpr int SEG_LOAD = 72;    // staged cells per segment (faces c0-1..c0+62 r
 #define TENO_NSEG_X 4
 #endif
 constexpr int NSEG_X = TENO_NSEG_X;  // segments per block, x-sweeps
-constexpr int NSEG_Y = 8;       // columns per block, y-sweeps (two per wave)
+#ifndef TENO_NSEG_Y
+#define TENO_NSEG_Y 8
+#endif
+constexpr int NSEG_Y = TENO_NSEG_Y;  // columns per block, y-sweeps
 constexpr int NCOPY = 64;       // spread copies of the wave-speed maxima (atomic contention)
 constexpr int NWORD = 16;       // words per copy: 0-3 x fields, 4-7 y fields, 8 CFL denominator
 
@@ -315,10 +318,12 @@ template <typename T> struct SweepArgs {
     int nx, ny;                 // grid
     int len, nlines;            // cells per line along the sweep, number of lines
     int nseg;                   // segments per line
+    int ntiles;                 // tiles of the sweep (persistent launches loop over them)
     int bc;                     // boundary condition along the sweep
     int bc_other;               // (unused by the sweep itself)
     int mode, stage, scheme, alpha_mode;
     T inv_h, eps, ct, gamma, adv;
+    T gm1;                      // gamma - 1
     T inv_dx, inv_dy;           // for the CFL denominator of the produced state
 };
 
@@ -342,7 +347,7 @@ __device__ __forceinline__ bool cell_speeds(const T *u, T gamma, T adv, T inv_dx
     } else {
         constexpr int NV = Sys<SYS>::NV;
         T rho = u[0], mx = u[1], my = NV == 4 ? u[2] : T(0), E = u[NV - 1];
-        T ir = T(1) / rho;
+        T ir = rho > T(0) ? recip(rho) : T(1) / rho;
         T vx = mx * ir, vy = my * ir;
         T p = (gamma - T(1)) * (E - T(0.5) * rho * (vx * vx + vy * vy));
         bool ok = rho > T(0) && p > T(0) && isfinite(E);
@@ -363,11 +368,85 @@ __device__ __forceinline__ bool cell_speeds(const T *u, T gamma, T adv, T inv_dx
     }
 }
 
+// Velocity components and sound speed of one cell (scalar systems: the characteristic speed in
+// sx, 0 elsewhere). Returns false for a non-physical or non-finite state.
+template <typename T, int SYS>
+__device__ __forceinline__ bool cell_primitive_speeds(const T *u, T gamma, T gm1, T adv, double &sx, double &sy,
+                                                      double &sc)
+{
+    if constexpr (SYS == ADV1D) {
+        sx = (double)adv; sy = 0.0; sc = 0.0;
+        return isfinite(u[0]);
+    } else if constexpr (SYS == BURGERS1D) {
+        sx = (double)u[0]; sy = 0.0; sc = 0.0;
+        return isfinite(u[0]);
+    } else {
+        constexpr int NV = Sys<SYS>::NV;
+        T rho = u[0], mx = u[1], my = NV == 4 ? u[2] : T(0), E = u[NV - 1];
+        T ir = rho > T(0) ? recip(rho) : T(1) / rho;
+        T vx = mx * ir, vy = my * ir;
+        T p = gm1 * (E - T(0.5) * rho * (vx * vx + vy * vy));
+        bool ok = rho > T(0) && p > T(0) && isfinite(E);
+        sc = (double)sqrt(gamma * p * ir);
+        sx = (double)vx;
+        sy = (double)vy;
+        return ok;
+    }
+}
+
+// Word q of the wave-speed record (same layout as cell_speeds): 0-3 |lambda| of the x fields,
+// 4-7 of the y fields, 8 the CFL denominator.
+template <int SYS>
+__device__ __forceinline__ double speed_word(int q, double ux, double uy, double c, double inv_dx, double inv_dy,
+                                             int alpha_mode)
+{
+    constexpr int NV = Sys<SYS>::NV;
+    if (SYS == ADV1D || SYS == BURGERS1D) return q == 0 ? fabs(ux) : (q == 8 ? fabs(ux) * inv_dx : 0.0);
+    if (q == 8) {
+        double w = (fabs(ux) + c) * inv_dx;
+        if (NV == 4) w = w + (fabs(uy) + c) * inv_dy;
+        return w;
+    }
+    const double un = q < 4 ? ux : uy;
+    if (alpha_mode) return fabs(un) + c;
+    const int f = q & 3;
+    if (NV == 3) return f == 0 ? fabs(un - c) : (f == 1 ? fabs(un) : (f == 2 ? fabs(un + c) : 0.0));
+    return f == 0 ? fabs(un - c) : (f == 3 ? fabs(un + c) : fabs(un));
+}
+
 __device__ __forceinline__ double wave_max(double v)
 {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, WAVE));
     return v;
+}
+
+// Data-parallel-primitive move of a double (two 32-bit halves); lanes without a source (outside
+// the row, or rows masked off) receive `fill`.
+template <int CTRL, int ROW_MASK = 0xf, int BANK_MASK = 0xf>
+__device__ __forceinline__ double dpp_mov(double x, double fill)
+{
+    const long long xv = __double_as_longlong(x), fv = __double_as_longlong(fill);
+    int lo = __builtin_amdgcn_update_dpp((int)fv, (int)xv, CTRL, ROW_MASK, BANK_MASK, false);
+    int hi = __builtin_amdgcn_update_dpp((int)(fv >> 32), (int)(xv >> 32), CTRL, ROW_MASK, BANK_MASK, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Maximum of a non-negative double over the wave (returned in every lane): running maxima inside
+// each 16-lane row by row shifts of 1, 2, 4, 8, then across rows by the row-15 and row-31
+// broadcasts, which leave the wave's maximum in lane 63.
+__device__ __forceinline__ double wave_max_nonneg(double v)
+{
+    v = fmax(v, dpp_mov<0x111>(v, 0.0));          // row_shr:1
+    v = fmax(v, dpp_mov<0x112>(v, 0.0));          // row_shr:2
+    v = fmax(v, dpp_mov<0x114>(v, 0.0));          // row_shr:4
+    v = fmax(v, dpp_mov<0x118>(v, 0.0));          // row_shr:8
+    v = fmax(v, dpp_mov<0x142, 0xa>(v, 0.0));     // row_bcast:15 into rows 1 and 3
+    v = fmax(v, dpp_mov<0x143, 0xc>(v, 0.0));     // row_bcast:31 into rows 2 and 3
+    const long long b = __double_as_longlong(v);
+    int lo = __builtin_amdgcn_readlane((int)b, 63);
+    int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
 // Block-wide maxima of nine per-lane values -> one atomicMax per word into one spread copy.
@@ -392,10 +471,10 @@ __device__ __forceinline__ void block_max_atomic(double w[9], unsigned long long
 //   FROZEN: the selection is read from masks_in instead of being measured.
 // ------------------------------------------------------------------------------------------------
 // Register budget of the sweep kernels: the minimum number of waves per SIMD the compiler must fit.
-// Measured on MI355X (2D Euler, FP64, 4096^2): 3 for both directions (the y-sweep's 8-column LDS
-// tile admits at most three blocks per CU; 4 makes the x-sweep spill).
+// Measured on MI355X (2D Euler, FP64, 4096^2): 4 for x-sweeps, 3 for y-sweeps (whose 8-column LDS
+// tile admits at most three blocks per CU); 1D Euler sweeps keep 3 (4 makes them spill).
 #ifndef TENO_MIN_WAVES_X
-#define TENO_MIN_WAVES_X 3
+#define TENO_MIN_WAVES_X 4
 #endif
 #ifndef TENO_MIN_WAVES_Y
 #define TENO_MIN_WAVES_Y 3
@@ -415,11 +494,13 @@ template <typename T> __device__ __forceinline__ void fill_coef(T *coef)
 
 // One tile of a sweep: NSEG line segments staged together in LDS. `tile` enumerates the tiles of
 // the sweep (x: NSEG consecutive segments of the row-major segment list; y: NSEG adjacent columns
-// at one segment position). rec/coef/red: the block's LDS; `copy`: the spread copy of the wave-speed
-// maxima this tile accumulates into (MODE_STAGE).
-template <typename T, int SYS, int DIR, bool FROZEN, int NSEG>
-__device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *rec, const T *coef, double *red,
-                                           unsigned long long *part_copy)
+// at one segment position). rec/coef/red: the block's LDS; MODE_STAGE accumulates the wave-speed
+// maxima of the produced cells into red (per-wave slots).
+// ext (x-sweeps with an RK stage or a y-part): LDS for the epilogue operands of the owned cells,
+// [NSEG][2][NV][WAVE] (U^n, then the y-part of dU/dt), loaded with the tile.
+template <typename T, int SYS, int DIR, bool FROZEN, int NSEG, int MODE>
+__device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *rec, T *ext, const T *coef,
+                                           double *red)
 {
     constexpr int NV = Sys<SYS>::NV;
     constexpr int SEG_STRIDE = seg_stride<SYS>();
@@ -466,7 +547,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
             T E = a.U[(size_t)(NV - 1) * ncell + off];
             T ir = T(1) / rho;
             T un = mn * ir, ut = mt * ir;
-            T p = (a.gamma - T(1)) * (E - T(0.5) * rho * (un * un + ut * ut));
+            T p = a.gm1 * (E - T(0.5) * rho * (un * un + ut * ut));
             if (!(rho > T(0) && p > T(0))) bad |= (isfinite(rho) && isfinite(p)) ? ERR_NONPHYSICAL : ERR_NONFINITE;
             r[0] = rho;
             r[SEG_LOAD * 1] = mn;
@@ -479,22 +560,44 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
             r[SEG_LOAD * S::H] = (E + p) * ir;
         }
     }
+    // epilogue operands of the owned cells (lanes 1..61), staged with the tile so that their
+    // latency overlaps the staging instead of the end of the face computation
+    constexpr bool HAS_EXT = DIR == 0 && MODE != MODE_FACES;
+    if constexpr (HAS_EXT) {
+        const bool want0 = MODE == MODE_STAGE, want1 = a.addend != nullptr;
+        if (want0 || want1) {
+            for (int idx = tid; idx < NSEG * SEG_CELLS; idx += BLOCK) {
+                const int s = idx / SEG_CELLS, kk = idx % SEG_CELLS + 1;
+                int line, c0;
+                seg_of(s, line, c0);
+                const int c = c0 - 1 + kk;
+                if (line < 0 || c >= a.len) continue;
+                const size_t off = (size_t)line * a.nx + c;
+                T *e = ext + (size_t)s * 2 * NV * WAVE + kk;
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    const size_t go = (size_t)gvar<SYS, DIR>(v) * ncell + off;
+                    if (want0) e[v * WAVE] = a.U0[go];
+                    if (want1) e[(NV + v) * WAVE] = a.addend[go];
+                }
+            }
+        }
+    }
     __syncthreads();
 
     const double *alpha = a.alpha + 4 * DIR;
-    double dtv = a.mode == MODE_STAGE ? *a.dt : 0.0;
-    double wmax[9];
-    for (int k = 0; k < 9; ++k) wmax[k] = 0.0;
+    double dtv = MODE == MODE_STAGE ? *a.dt : 0.0;
 
-    for (int s = wid; s < NSEG; s += BLOCK / WAVE) {
+    // the segment loop is wave-uniform: keep its indices in scalar registers
+    for (int s = __builtin_amdgcn_readfirstlane(wid); s < NSEG; s += BLOCK / WAVE) {
         int line, c0;
         seg_of(s, line, c0);
         if (line < 0) continue;                 // wave-uniform
         const T *R0 = rec + s * SEG_STRIDE;
         const int k = lane;
         const int f = c0 - 1 + k;               // this lane's face
-        const bool face_ok = k >= 1 && k <= 62 && f <= a.len;
-        const bool cell_ok = k >= 1 && k <= 61 && f < a.len;
+        bool face_ok = k >= 1 && k <= 62 && f <= a.len;
+        bool cell_ok = k >= 1 && k <= 61 && f < a.len;
         size_t fidx = 0;                        // face index in this direction's face arrays
         if (face_ok) fidx = DIR == 0 ? (size_t)line * (a.len + 1) + f : (size_t)f * a.nx + line;
         uint32_t mword_in = 0;
@@ -505,23 +608,11 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
         for (int v = 0; v < NV; ++v) Fh[v] = T(0);
         uint32_t mword = 0, fword = 0;
 
-        // epilogue operands (RK base state, other direction's part) fetched now, consumed after
-        // the face computation, so that their latency overlaps it
-        // (x-sweeps only: the y-sweep never has either)
-        T pre0[NV], pre1[NV];
-        const size_t coff = DIR == 0 ? (size_t)line * a.nx + f : (size_t)f * a.nx + line;
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            const size_t go = (size_t)gvar<SYS, DIR>(v) * ncell + coff;
-            pre0[v] = (DIR == 0 && cell_ok && a.mode == MODE_STAGE) ? a.U0[go] : T(0);
-            pre1[v] = (DIR == 0 && cell_ok && a.addend) ? a.addend[go] : T(0);
-        }
-
         // Roe-averaged state of the face (cells i = q k+3 and i+1 = q k+4, Remark 3)
         Roe<T> roe;
         if constexpr (EULER) {
             using S = Sys<SYS>;
-            const T gm1 = a.gamma - T(1);
+            const T gm1 = a.gm1;
             T sL = R0[SEG_LOAD * S::S + k + 3], sR = R0[SEG_LOAD * S::S + k + 4];
             T isum = T(1) / (sL + sR);
             roe.un = (sL * R0[SEG_LOAD * S::UN + k + 3] + sR * R0[SEG_LOAD * S::UN + k + 4]) * isum;
@@ -652,7 +743,16 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
         }
 
         // ---- epilogue ----
-        if (a.mode == MODE_FACES) {
+        // lane-dependent predicates recomputed from an opaque copy of the lane id (keeping them
+        // live across the field loop costs registers the loop needs)
+        {
+            int kk = lane;
+            asm volatile("" : "+v"(kk));
+            const int ff = c0 - 1 + kk;
+            face_ok = kk >= 1 && kk <= 62 && ff <= a.len;
+            cell_ok = kk >= 1 && kk <= 61 && ff < a.len;
+        }
+        if constexpr (MODE == MODE_FACES) {
             if (face_ok) {
 #pragma unroll
                 for (int v = 0; v < NV; ++v) {
@@ -665,24 +765,27 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
             }
         }
         if (a.masks_out && face_ok) a.masks_out[fidx] = mword;
-        if (a.mode != MODE_FACES) {
+        if constexpr (MODE != MODE_FACES) {
             T Fr[NV];
 #pragma unroll
             for (int v = 0; v < NV; ++v) Fr[v] = shfl_dn1(Fh[v]);
+            // primitive speeds of the produced cell (stage mode); lanes without a cell contribute 0
+            double sx = 0.0, sy = 0.0, sc = 0.0;
             if (cell_ok) {
                 size_t off = DIR == 0 ? (size_t)line * a.nx + f : (size_t)f * a.nx + line;
+                const T *e = ext + (size_t)s * 2 * NV * WAVE + k;
                 T unew[NV];
 #pragma unroll
                 for (int v = 0; v < NV; ++v) {
                     const size_t go = (size_t)gvar<SYS, DIR>(v) * ncell + off;
                     T d = -(Fr[v] - Fh[v]) * a.inv_h;
-                    if (a.addend) d = d + (DIR == 0 ? pre1[v] : a.addend[go]);
-                    if (a.mode == MODE_RHS) {
+                    if (a.addend) d = d + (HAS_EXT ? e[(NV + v) * WAVE] : a.addend[go]);
+                    if constexpr (MODE == MODE_RHS) {
                         a.out[go] = d;
                     } else {
                         // SSP-RK3 stage, Shu-Osher form
                         T uk = R0[SEG_LOAD * v + k + 4];   // staged record: conserved variable v first
-                        T u0 = DIR == 0 ? pre0[v] : a.U0[go];
+                        T u0 = HAS_EXT ? e[v * WAVE] : a.U0[go];
                         T dt = (T)dtv;
                         T un;
                         if (a.stage == 0) un = u0 + dt * d;
@@ -692,30 +795,81 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
                         unew[gvar<SYS, DIR>(v)] = un;
                     }
                 }
-                if (a.mode == MODE_STAGE) {
-                    double w9[9];
-                    bool ok = cell_speeds<T, SYS>(unew, a.gamma, a.adv, a.inv_dx, a.inv_dy, a.alpha_mode, w9);
-                    if (!ok) bad |= ERR_NONPHYSICAL;
+                if constexpr (MODE == MODE_STAGE) {
+                    if (!cell_primitive_speeds<T, SYS>(unew, a.gamma, a.gm1, a.adv, sx, sy, sc)) bad |= ERR_NONPHYSICAL;
+                }
+            }
+            if constexpr (MODE == MODE_STAGE) {
+                // this segment's maxima into the wave's LDS slot (the wave owns it: no race), one word
+                // at a time so that only the three speeds stay live
 #pragma unroll
-                    for (int q = 0; q < 9; ++q) wmax[q] = fmax(wmax[q], w9[q]);
+                for (int q = 0; q < 9; ++q) {
+                    const bool dup = NV == 4 && (q == 2 || q == 6);
+                    const bool unused = (NV == 3 && q >= 3 && q < 8) || (NV == 1 && q >= 1 && q < 8);
+                    if (dup || unused) continue;
+                    double val = speed_word<SYS>(q, sx, sy, sc, (double)a.inv_dx, (double)a.inv_dy, a.alpha_mode);
+                    double m = wave_max_nonneg(cell_ok ? val : 0.0);
+                    if (lane == 0) {
+                        red[wid * 9 + q] = fmax(red[wid * 9 + q], m);
+                        if (NV == 4 && (q == 1 || q == 5)) red[wid * 9 + q + 1] = fmax(red[wid * 9 + q + 1], m);
+                    }
                 }
             }
         }
     }
-    if (a.mode == MODE_STAGE) block_max_atomic(wmax, part_copy, red);
     if (bad) atomicOr(a.err, bad);
 }
 
-template <typename T, int SYS, int DIR, bool FROZEN>
-__global__ void __launch_bounds__(BLOCK, DIR == 0 ? TENO_MIN_WAVES_X : TENO_MIN_WAVES_Y) sweep_kernel(SweepArgs<T> a)
+// Per-wave maxima slots of a block (MODE_STAGE): cleared before the first tile, flushed (one
+// atomic maximum per word into a spread copy) when the block is done with an instance.
+__device__ __forceinline__ void clear_maxima(double *red)
+{
+    if (threadIdx.x < BLOCK / WAVE * 9) red[threadIdx.x] = 0.0;
+    __syncthreads();
+}
+
+__device__ __forceinline__ void flush_maxima(double *red, unsigned long long *copy)
+{
+    __syncthreads();
+    if (threadIdx.x < 9) {
+        double m = 0.0;
+        for (int q = 0; q < BLOCK / WAVE; ++q) m = fmax(m, red[q * 9 + threadIdx.x]);
+        atomicMax(copy + threadIdx.x, (unsigned long long)__double_as_longlong(m));
+    }
+    __syncthreads();
+    if (threadIdx.x < BLOCK / WAVE * 9) red[threadIdx.x] = 0.0;
+    __syncthreads();
+}
+
+// LDS of the epilogue operands (x-sweeps that add a y-part or apply an RK stage).
+template <typename T, int SYS, int DIR, int NSEG, int MODE> constexpr int ext_size()
+{
+    return (DIR == 0 && MODE != MODE_FACES) ? NSEG * 2 * Sys<SYS>::NV * WAVE : 1;
+}
+
+// One tile per block (measured faster on MI355X than persistent blocks looping over tiles: freshly
+// scheduled blocks overlap their staging with the compute of resident ones).
+template <typename T, int SYS, int DIR, bool FROZEN, int MODE>
+__global__ void __launch_bounds__(BLOCK, SYS == EULER1D ? 3 : (DIR == 0 ? TENO_MIN_WAVES_X : TENO_MIN_WAVES_Y))
+    sweep_kernel(SweepArgs<T> a)
 {
     constexpr int NSEG = DIR == 0 ? NSEG_X : NSEG_Y;
     __shared__ T rec[NSEG * seg_stride<SYS>()];
+    __shared__ T ext[ext_size<T, SYS, DIR, NSEG, MODE>()];
     __shared__ T coef[NCOEF_ROWS * 8];
     __shared__ double red[BLOCK / WAVE * 9];
     fill_coef(coef);
-    sweep_tile<T, SYS, DIR, FROZEN, NSEG>(a, blockIdx.x, rec, coef, red,
-                                          a.part ? a.part + (size_t)(blockIdx.x % NCOPY) * NWORD : nullptr);
+    if (MODE == MODE_STAGE && threadIdx.x < BLOCK / WAVE * 9) red[threadIdx.x] = 0.0;   // ordered by the
+    sweep_tile<T, SYS, DIR, FROZEN, NSEG, MODE>(a, blockIdx.x, rec, ext, coef, red);      // staging barrier
+    if (MODE == MODE_STAGE) {
+        __syncthreads();
+        if (threadIdx.x < 9) {
+            double m = 0.0;
+            for (int q = 0; q < BLOCK / WAVE; ++q) m = fmax(m, red[q * 9 + threadIdx.x]);
+            unsigned long long *copy = a.part + (size_t)(blockIdx.x % NCOPY) * NWORD;
+            atomicMax(copy + threadIdx.x, (unsigned long long)__double_as_longlong(m));
+        }
+    }
 }
 
 // ------------------------------------------------------------------------------------------------

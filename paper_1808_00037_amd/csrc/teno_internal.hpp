@@ -13,6 +13,7 @@ struct teno_ctx {
     teno_opts opts;
     hipStream_t stream = nullptr;
     int nv = 1;
+    int num_cu = 256;
     double dx = 1, dy = 1, eps_x = 0, eps_y = 0;
     size_t ncell = 0, nelem = 0, nfx = 0, nfy = 0, esize = 8;
     teno::Ctrl *ctrl_d = nullptr;

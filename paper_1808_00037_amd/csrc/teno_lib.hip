@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -130,20 +131,27 @@ static void launch_sweep_t(teno_ctx *c, const SweepReq &r)
     a.eps = (T)(DIR == 0 ? c->eps_x : c->eps_y);
     a.ct = (T)c->opts.ct;
     a.gamma = (T)c->opts.gamma;
+    a.gm1 = (T)(c->opts.gamma - 1.0);
     a.adv = (T)c->opts.adv_speed;
     a.inv_dx = (T)(1.0 / c->dx);
     a.inv_dy = (T)(1.0 / c->dy);
-    unsigned nblocks;
+    size_t ntiles;
     if (DIR == 0) {
         size_t nseg_total = (size_t)a.nseg * a.nlines;
-        nblocks = (unsigned)((nseg_total + NSEG_X - 1) / NSEG_X);
+        ntiles = (nseg_total + NSEG_X - 1) / NSEG_X;
     } else {
-        size_t ntile = (size_t)(a.nlines + NSEG_Y - 1) / NSEG_Y;
-        nblocks = (unsigned)(ntile * a.nseg);
+        ntiles = (size_t)((a.nlines + NSEG_Y - 1) / NSEG_Y) * a.nseg;
     }
+    a.ntiles = (int)ntiles;
     std::pair<hipEvent_t, hipEvent_t> *ev = teno_timing_slot(c, DIR);
     if (ev) (void)hipEventRecord(ev->first, c->stream);
-    hipLaunchKernelGGL((sweep_kernel<T, SYS, DIR, FROZEN>), dim3(nblocks), dim3(BLOCK), 0, c->stream, a);
+    const dim3 grid((unsigned)ntiles);
+    if (r.mode == MODE_RHS)
+        hipLaunchKernelGGL((sweep_kernel<T, SYS, DIR, FROZEN, MODE_RHS>), grid, dim3(BLOCK), 0, c->stream, a);
+    else if (DIR == 0 && r.mode == MODE_STAGE)
+        hipLaunchKernelGGL((sweep_kernel<T, SYS, 0, FROZEN, MODE_STAGE>), grid, dim3(BLOCK), 0, c->stream, a);
+    else
+        hipLaunchKernelGGL((sweep_kernel<T, SYS, DIR, FROZEN, MODE_FACES>), grid, dim3(BLOCK), 0, c->stream, a);
     if (ev) (void)hipEventRecord(ev->second, c->stream);
 }
 
@@ -179,7 +187,7 @@ template <typename T>
 static void launch_wavespeed_t(teno_ctx *c, const void *U, int ring)
 {
     size_t nb = (c->ncell + BLOCK - 1) / BLOCK;
-    unsigned grid = (unsigned)(nb < 2048 ? (nb ? nb : 1) : 2048);
+    unsigned grid = (unsigned)(nb < 1024 ? (nb ? nb : 1) : 1024);
     unsigned long long *part = &c->ctrl_d->part[ring][0][0];
     const T g = (T)c->opts.gamma, adv = (T)c->opts.adv_speed, ix = (T)(1.0 / c->dx), iy = (T)(1.0 / c->dy);
     const T *u = (const T *)U;
@@ -354,6 +362,12 @@ teno_status teno_create(const teno_grid *grid, const teno_opts *opts, void *stre
     c->opts = *opts;
     c->stream = (hipStream_t)stream;
     teno_fill_derived(c);
+    {
+        int dev = 0, cu = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cu > 0)
+            c->num_cu = cu;
+    }
     if (hipMalloc(&c->ctrl_d, sizeof(Ctrl)) != hipSuccess) {
         delete c;
         return TENO_E_HIP;
