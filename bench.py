@@ -53,17 +53,27 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_x_stage_euler2d_4096_traffic.txt")
+
+
 def measured_traffic():
     """HBM bytes per launch of the x-sweep stage kernel from the committed rocprofv3 --pmc
-    summary, if it was taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", "sweep_x_stage_euler2d_4096_traffic.json")
-    if not os.path.exists(path):
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by the same counters' reading for a plain copy
+    kernel), if it was taken on the current kernel source; else None."""
+    if not os.path.exists(TRAFFIC_FILE):
         return None
-    with open(path) as fh:
-        d = json.load(fh)
-    if d.get("kernel_source_sha") != kernel_source_hash():
+    kv = {}
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha") != kernel_source_hash():
         return None
-    return d.get("bytes_per_launch")
+    try:
+        return float(kv["bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(problem, budget_s=12.0):
@@ -233,16 +243,22 @@ def main():
     value = cells * 3 * args.steps / (ms / 1e3) / 1e9
     log(f"{ms_per_step:.3f} ms/step, {value:.2f} Gcell-updates/s (wall {wall:.2f} s)")
 
-    # per-kernel durations, HIP events on the launch stream, eager launches of the same steps
-    ksteps = min(args.steps, 10)
+    # per-kernel durations: the same K steps again, launched one kernel at a time with HIP events
+    # recorded around every sweep launch on the stream the kernels run on
     sv.set_timing(True)
-    sv.run(U, ksteps, graph=False)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    sv.run(U, args.steps, graph=False)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_eager = e0.elapsed_time(e1)
     kt = sv.read_timing()
     sv.set_timing(False)
     sv.poll()
     x_ms = kt["x"][0] / max(kt["x"][1], 1)
     y_ms = kt["y"][0] / max(kt["y"][1], 1)
-    log(f"x-sweep+stage {x_ms:.3f} ms, y-sweep {y_ms:.3f} ms per launch")
+    log(f"x-sweep+stage {x_ms:.3f} ms, y-sweep {y_ms:.3f} ms per launch ({kt['x'][1]} + {kt['y'][1]} launches), "
+        f"eager step {ms_eager / args.steps:.3f} ms")
     flops_x = FLOPS_XSTAGE * cells
     achieved = flops_x / (x_ms / 1e3)
     roofline = {"bound": "alu", "kernel": "sweep_kernel<double,EULER2D,x,stage>", "achieved": achieved / 1e12,
@@ -259,13 +275,15 @@ def main():
            "roofline": roofline,
            "hbm": {"algorithmic_bytes_per_cell_update": BYTES_PER_CELL_UPDATE,
                    "achieved_GBps": value * BYTES_PER_CELL_UPDATE, "peak_GBps": PEAK_HBM / 1e9, "frac": hbm_frac},
-           "kernels_ms": {"x_sweep_stage": x_ms, "y_sweep": y_ms}}
+           "kernels_ms": {"x_sweep_stage": x_ms, "y_sweep": y_ms, "launches_x": kt["x"][1],
+                          "launches_y": kt["y"][1], "eager_ms_per_step": ms_eager / args.steps}}
 
     if args.copy_bytes > 0:
+        # an elementwise kernel that reads copy_bytes and writes copy_bytes
         src = torch.ones(args.copy_bytes // 8, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
-        dst.copy_(src)
+        torch.mul(src, 1.0, out=dst)
         torch.cuda.synchronize()
         del src, dst
     del sv, U

@@ -587,6 +587,10 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
 
     const double *alpha = a.alpha + 4 * DIR;
     double dtv = MODE == MODE_STAGE ? *a.dt : 0.0;
+    // y-sweeps producing dU/dt leave their results in the segment's own LDS record and store the
+    // tile row by row at the end (a lane's cells run down a column: direct stores would be strided)
+    constexpr bool STAGE_OUT = DIR == 1 && MODE == MODE_RHS;
+    static_assert(NV * SEG_CELLS <= SEG_STRIDE, "staged output must fit in a segment record");
 
     // the segment loop is wave-uniform: keep its indices in scalar registers
     for (int s = __builtin_amdgcn_readfirstlane(wid); s < NSEG; s += BLOCK / WAVE) {
@@ -747,7 +751,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
         // live across the field loop costs registers the loop needs)
         {
             int kk = lane;
-            asm volatile("" : "+v"(kk));
+            asm volatile("" : "+v"(kk) : : "memory");   // also orders the record reads before the epilogue
             const int ff = c0 - 1 + kk;
             face_ok = kk >= 1 && kk <= 62 && ff <= a.len;
             cell_ok = kk >= 1 && kk <= 61 && ff < a.len;
@@ -780,7 +784,9 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
                     const size_t go = (size_t)gvar<SYS, DIR>(v) * ncell + off;
                     T d = -(Fr[v] - Fh[v]) * a.inv_h;
                     if (a.addend) d = d + (HAS_EXT ? e[(NV + v) * WAVE] : a.addend[go]);
-                    if constexpr (MODE == MODE_RHS) {
+                    if constexpr (STAGE_OUT) {
+                        rec[s * SEG_STRIDE + v * SEG_CELLS + k - 1] = d;   // own record, no longer read
+                    } else if constexpr (MODE == MODE_RHS) {
                         a.out[go] = d;
                     } else {
                         // SSP-RK3 stage, Shu-Osher form
@@ -817,6 +823,17 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
             }
         }
     }
+    if constexpr (STAGE_OUT) {
+        __syncthreads();
+        for (int idx = tid; idx < NV * SEG_CELLS * NSEG; idx += BLOCK) {
+            const int sg = idx % NSEG, c = (idx / NSEG) % SEG_CELLS, v = idx / (NSEG * SEG_CELLS);
+            int line, c0;
+            seg_of(sg, line, c0);
+            if (line < 0 || c0 + c >= a.len) continue;
+            a.out[(size_t)gvar<SYS, DIR>(v) * ncell + (size_t)(c0 + c) * a.nx + line] =
+                rec[sg * SEG_STRIDE + v * SEG_CELLS + c];
+        }
+    }
     if (bad) atomicOr(a.err, bad);
 }
 
@@ -841,6 +858,17 @@ __device__ __forceinline__ void flush_maxima(double *red, unsigned long long *co
     __syncthreads();
 }
 
+// Workgroups of a launch are handed to the 8 XCDs round-robin (block b to XCD b mod 8), and each
+// XCD has its own L2. Renumber so that every XCD walks a contiguous range of tiles in order:
+// neighbouring tiles, which share cache lines and halo cells, then meet in the same L2. A bijection
+// of [0, n) for any n.
+constexpr int NXCD = 8;
+__device__ __forceinline__ int xcd_tile(int b, int n)
+{
+    const int q = n / NXCD, r = n % NXCD, x = b % NXCD;
+    return x * q + min(x, r) + b / NXCD;
+}
+
 // LDS of the epilogue operands (x-sweeps that add a y-part or apply an RK stage).
 template <typename T, int SYS, int DIR, int NSEG, int MODE> constexpr int ext_size()
 {
@@ -860,7 +888,8 @@ __global__ void __launch_bounds__(BLOCK, SYS == EULER1D ? 3 : (DIR == 0 ? TENO_M
     __shared__ double red[BLOCK / WAVE * 9];
     fill_coef(coef);
     if (MODE == MODE_STAGE && threadIdx.x < BLOCK / WAVE * 9) red[threadIdx.x] = 0.0;   // ordered by the
-    sweep_tile<T, SYS, DIR, FROZEN, NSEG, MODE>(a, blockIdx.x, rec, ext, coef, red);      // staging barrier
+    sweep_tile<T, SYS, DIR, FROZEN, NSEG, MODE>(a, xcd_tile(blockIdx.x, gridDim.x), rec, ext, coef,
+                                                red);                                     // staging barrier
     if (MODE == MODE_STAGE) {
         __syncthreads();
         if (threadIdx.x < 9) {
