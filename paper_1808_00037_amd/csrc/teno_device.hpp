@@ -421,32 +421,30 @@ __device__ __forceinline__ double wave_max(double v)
     return v;
 }
 
-// Data-parallel-primitive move of a double (two 32-bit halves); lanes without a source (outside
-// the row, or rows masked off) receive `fill`.
-template <int CTRL, int ROW_MASK = 0xf, int BANK_MASK = 0xf>
-__device__ __forceinline__ double dpp_mov(double x, double fill)
+// Maximum of an unsigned word over the wave (returned in every lane): running maxima inside each
+// 16-lane row by row shifts of 1, 2, 4, 8, then across rows by the row-15 and row-31 broadcasts,
+// which leave the wave's maximum in lane 63. Lanes without a source read 0, the identity.
+__device__ __forceinline__ unsigned wave_max_u32(unsigned v)
 {
-    const long long xv = __double_as_longlong(x), fv = __double_as_longlong(fill);
-    int lo = __builtin_amdgcn_update_dpp((int)fv, (int)xv, CTRL, ROW_MASK, BANK_MASK, false);
-    int hi = __builtin_amdgcn_update_dpp((int)(fv >> 32), (int)(xv >> 32), CTRL, ROW_MASK, BANK_MASK, false);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false));   // row_shr:1
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false));   // row_shr:2
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false));   // row_shr:4
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false));   // row_shr:8
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false));   // row_bcast:15
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false));   // row_bcast:31
+    return (unsigned)__builtin_amdgcn_readlane((int)v, 63);
 }
 
-// Maximum of a non-negative double over the wave (returned in every lane): running maxima inside
-// each 16-lane row by row shifts of 1, 2, 4, 8, then across rows by the row-15 and row-31
-// broadcasts, which leave the wave's maximum in lane 63.
-__device__ __forceinline__ double wave_max_nonneg(double v)
+// Maximum over the wave of a finite non-negative double. Such doubles order like their bit
+// patterns, so the maximum is taken on the high words, then on the low words of the lanes that
+// hold the maximal high word: exact, and without floating-point compares.
+__device__ __forceinline__ double wave_max_nonneg(double x)
 {
-    v = fmax(v, dpp_mov<0x111>(v, 0.0));          // row_shr:1
-    v = fmax(v, dpp_mov<0x112>(v, 0.0));          // row_shr:2
-    v = fmax(v, dpp_mov<0x114>(v, 0.0));          // row_shr:4
-    v = fmax(v, dpp_mov<0x118>(v, 0.0));          // row_shr:8
-    v = fmax(v, dpp_mov<0x142, 0xa>(v, 0.0));     // row_bcast:15 into rows 1 and 3
-    v = fmax(v, dpp_mov<0x143, 0xc>(v, 0.0));     // row_bcast:31 into rows 2 and 3
-    const long long b = __double_as_longlong(v);
-    int lo = __builtin_amdgcn_readlane((int)b, 63);
-    int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+    const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+    const unsigned hi = (unsigned)(b >> 32), lo = (unsigned)b;
+    const unsigned mh = wave_max_u32(hi);
+    const unsigned ml = wave_max_u32(hi == mh ? lo : 0u);
+    return __longlong_as_double((long long)(((unsigned long long)mh << 32) | ml));
 }
 
 // Block-wide maxima of nine per-lane values -> one atomicMax per word into one spread copy.
@@ -802,19 +800,36 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
                     }
                 }
                 if constexpr (MODE == MODE_STAGE) {
-                    if (!cell_primitive_speeds<T, SYS>(unew, a.gamma, a.gm1, a.adv, sx, sy, sc)) bad |= ERR_NONPHYSICAL;
+                    if (!cell_primitive_speeds<T, SYS>(unew, a.gamma, a.gm1, a.adv, sx, sy, sc)) {
+                        bad |= ERR_NONPHYSICAL;       // reported; keep the maxima finite
+                        sx = sy = sc = 0.0;
+                    }
                 }
             }
             if constexpr (MODE == MODE_STAGE) {
-                // this segment's maxima into the wave's LDS slot (the wave owns it: no race), one word
-                // at a time so that only the three speeds stay live
+                // this segment's maxima into the wave's LDS slot (the wave owns it: no race); the
+                // words are reduced side by side so that their cross-lane steps interleave
+                constexpr bool USE[9] = {true, NV != 1, NV == 3, NV == 4, NV == 4, NV == 4, false, NV == 4, true};
+                unsigned hi[9], lo[9], mh[9], ml[9];
 #pragma unroll
                 for (int q = 0; q < 9; ++q) {
-                    const bool dup = NV == 4 && (q == 2 || q == 6);
-                    const bool unused = (NV == 3 && q >= 3 && q < 8) || (NV == 1 && q >= 1 && q < 8);
-                    if (dup || unused) continue;
-                    double val = speed_word<SYS>(q, sx, sy, sc, (double)a.inv_dx, (double)a.inv_dy, a.alpha_mode);
-                    double m = wave_max_nonneg(cell_ok ? val : 0.0);
+                    if (!USE[q]) continue;
+                    const double val = cell_ok ? speed_word<SYS>(q, sx, sy, sc, (double)a.inv_dx, (double)a.inv_dy,
+                                                                 a.alpha_mode) : 0.0;
+                    const unsigned long long b = (unsigned long long)__double_as_longlong(val);
+                    hi[q] = (unsigned)(b >> 32);
+                    lo[q] = (unsigned)b;
+                }
+#pragma unroll
+                for (int q = 0; q < 9; ++q)
+                    if (USE[q]) mh[q] = wave_max_u32(hi[q]);
+#pragma unroll
+                for (int q = 0; q < 9; ++q)
+                    if (USE[q]) ml[q] = wave_max_u32(hi[q] == mh[q] ? lo[q] : 0u);
+#pragma unroll
+                for (int q = 0; q < 9; ++q) {
+                    if (!USE[q]) continue;
+                    const double m = __longlong_as_double((long long)(((unsigned long long)mh[q] << 32) | ml[q]));
                     if (lane == 0) {
                         red[wid * 9 + q] = fmax(red[wid * 9 + q], m);
                         if (NV == 4 && (q == 1 || q == 5)) red[wid * 9 + q + 1] = fmax(red[wid * 9 + q + 1], m);
