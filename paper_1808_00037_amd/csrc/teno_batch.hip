@@ -64,6 +64,7 @@ template <typename T> struct BatchSweep {
     unsigned *err;
     int mode, stage, ring_next, scheme, alpha_mode;
     T ct, gamma;
+    T smooth_k;                     // all-smooth shortcut factor for ct
 };
 
 int nseg_of(int len) { return (len + SEG_CELLS - 1) / SEG_CELLS; }
@@ -112,6 +113,7 @@ __device__ __forceinline__ SweepArgs<T> item_args(const BatchSweep<T> &b, const 
     a.inv_h = (T)(DIR == 0 ? I.inv_dx : I.inv_dy);
     a.eps = (T)(DIR == 0 ? I.eps_x : I.eps_y);
     a.ct = b.ct;
+    a.smooth_k = b.smooth_k;
     a.gamma = b.gamma;
     a.gm1 = b.gamma - T(1);
     a.adv = T(1);
@@ -260,6 +262,7 @@ BatchSweep<T> base_args(const teno_batch *b)
     a.scheme = b->opts.scheme;
     a.alpha_mode = b->opts.alpha_mode;
     a.ct = (T)b->opts.ct;
+    a.smooth_k = (T)smooth_shortcut_k(b->opts.ct);
     a.gamma = (T)b->opts.gamma;
     return a;
 }

@@ -177,8 +177,10 @@ __device__ __forceinline__ int table3(unsigned idx)
 //
 // smooth5() computes beta_0..2 and tau5 = |beta_0 - beta_2|. Exact shortcut: with
 // r_k = 1 + tau5/(beta_k + eps) >= 1, the smallest chi_k is at least
-// 1 / (1 + 2 (r_max/r_min)^6); if tau5 <= 5 (min_k beta_k + eps) then r_max/r_min <= 6 and
-// chi_min >= 1/93313 > C_T (1e-5) with a 7% margin, so every delta_k = 1 whatever the rounding.
+// 1 / (1 + 2 (r_max/r_min)^6); if tau5 <= K (min_k beta_k + eps) then r_max/r_min <= 1 + K and
+// chi_min >= 1 / (1 + 2 (1 + K)^6). K is chosen on the host from C_T (smooth_shortcut_k) with a
+// margin that covers rounding, so every delta_k = 1 on that branch (C_T = 1e-5: K = 5.0, chi_min
+// >= 1/93313).
 // cutoff3() evaluates the definition: delta_k = 0 iff gamma_k / sum(gamma) < C_T, computed as
 // gamma_k < C_T * sum(gamma) with gamma_k = (1 + tau (D_j D_l) / (D0 D1 D2))^6, D_k = beta_k + eps:
 // one reciprocal per side instead of six divisions; equal to the definition up to rounding, so a
@@ -201,10 +203,19 @@ __device__ __forceinline__ Smooth<T> smooth5(T a, T b, T c, T d, T e)
 }
 
 template <typename T>
-__device__ __forceinline__ bool all_smooth(const Smooth<T> &m, T eps)
+__device__ __forceinline__ bool all_smooth(const Smooth<T> &m, T eps, T k)
 {
     T bmin = fmin(m.b0, fmin(m.b1, m.b2));
-    return m.tau <= T(5) * (bmin + eps);
+    return m.tau <= k * (bmin + eps);
+}
+
+// Largest K of the shortcut for cut-off ct: 1 / (1 + 2 (1 + K)^6) >= ct must hold with room for
+// rounding; taken 1% below the bound and capped at 5.
+inline double smooth_shortcut_k(double ct)
+{
+    double kmax = pow((1.0 / ct - 1.0) * 0.5, 1.0 / 6.0) - 1.0;
+    double k = 0.99 * kmax;
+    return k < 0.0 ? 0.0 : (k > 5.0 ? 5.0 : k);
 }
 
 // Reciprocal from the hardware estimate and two Newton steps (argument normal and positive).
@@ -323,6 +334,7 @@ template <typename T> struct SweepArgs {
     int bc_other;               // (unused by the sweep itself)
     int mode, stage, scheme, alpha_mode;
     T inv_h, eps, ct, gamma, adv;
+    T smooth_k;                 // all-smooth shortcut factor for ct (smooth_shortcut_k)
     T gm1;                      // gamma - 1
     T inv_dx, inv_dy;           // for the CFL denominator of the produced state
 };
@@ -684,7 +696,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
             } else {
                 Smooth<T> sp = smooth5(vp[1], vp[2], vp[3], vp[4], vp[5]);
                 Smooth<T> sm = smooth5(vm[6], vm[5], vm[4], vm[3], vm[2]);
-                const bool easy = all_smooth(sp, a.eps) && all_smooth(sm, a.eps);
+                const bool easy = all_smooth(sp, a.eps, a.smooth_k) && all_smooth(sm, a.eps, a.smooth_k);
                 if (__all(easy)) {
                     // every flag of every face of the wave is 1: the full stencil on both sides
                     fword |= 63u << (6 * sf);

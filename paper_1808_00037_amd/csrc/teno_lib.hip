@@ -130,6 +130,7 @@ static void launch_sweep_t(teno_ctx *c, const SweepReq &r)
     a.inv_h = (T)(1.0 / (DIR == 0 ? c->dx : c->dy));
     a.eps = (T)(DIR == 0 ? c->eps_x : c->eps_y);
     a.ct = (T)c->opts.ct;
+    a.smooth_k = (T)smooth_shortcut_k(c->opts.ct);
     a.gamma = (T)c->opts.gamma;
     a.gm1 = (T)(c->opts.gamma - 1.0);
     a.adv = (T)c->opts.adv_speed;

@@ -17,14 +17,14 @@ from paper_1808_00037_amd import teno as T
 REL_TOL = 1e-12
 
 
-def oracle_cfg(pr, scheme=O.TENO7X, eps=None, alpha_mode=0):
+def oracle_cfg(pr, scheme=O.TENO7X, eps=None, alpha_mode=0, ct=1e-5):
     return O.Config(pr.sys, pr.nx, pr.ny, pr.x0, pr.x1, pr.y0, pr.y1, pr.bc_x, pr.bc_y, scheme=scheme,
-                    alpha_mode=alpha_mode, gamma=pr.gamma, eps=eps)
+                    alpha_mode=alpha_mode, gamma=pr.gamma, eps=eps, ct=ct)
 
 
-def solver_for(pr, dtype=torch.float64, scheme=T.TENO7X, eps=None, alpha_mode=0):
+def solver_for(pr, dtype=torch.float64, scheme=T.TENO7X, eps=None, alpha_mode=0, ct=1e-5):
     return T.Solver(pr.sys, pr.nx, pr.ny, pr.x0, pr.x1, pr.y0, pr.y1, pr.bc_x, pr.bc_y, dtype=dtype,
-                    scheme=scheme, eps=eps, alpha_mode=alpha_mode, cfl=pr.cfl, gamma=pr.gamma)
+                    scheme=scheme, eps=eps, alpha_mode=alpha_mode, cfl=pr.cfl, gamma=pr.gamma, ct=ct)
 
 
 def _phys_flux_mag(sys, U, direction, gamma=1.4, adv=1.0):
@@ -65,11 +65,11 @@ def face_scale(pr, U, direction):
     return out
 
 
-def compare_faces(pr, U_np, scheme=O.TENO7X, eps=None, alpha_mode=0, solver=None):
+def compare_faces(pr, U_np, scheme=O.TENO7X, eps=None, alpha_mode=0, solver=None, ct=1e-5):
     """Run both sides on one state; return a report dict (asserting nothing)."""
-    cfg = oracle_cfg(pr, scheme, eps, alpha_mode)
+    cfg = oracle_cfg(pr, scheme, eps, alpha_mode, ct)
     _, ex = O.rhs(cfg, U_np, want_faces=True)
-    sv = solver or solver_for(pr, scheme=scheme, eps=eps, alpha_mode=alpha_mode)
+    sv = solver or solver_for(pr, scheme=scheme, eps=eps, alpha_mode=alpha_mode, ct=ct)
     U = torch.from_numpy(np.ascontiguousarray(U_np)).cuda()
     g = sv.face_fluxes(U)
     torch.cuda.synchronize()
@@ -93,7 +93,7 @@ def compare_faces(pr, U_np, scheme=O.TENO7X, eps=None, alpha_mode=0, solver=None
         for idx in np.argwhere(fdiff):
             x = int(fg[tuple(idx)] ^ fo[tuple(idx)])
             bits = [b for b in range(24) if (x >> b) & 1]   # bit 6s+3side+k <-> chi[..., 6s+3side+k]
-            if all(abs(chi[tuple(idx)][b] / 1e-5 - 1.0) < 1e-9 for b in bits):
+            if all(abs(chi[tuple(idx)][b] / ct - 1.0) < 1e-9 for b in bits):
                 rep["flips_near_ct"] += 1
         # masks are a function of the flags of a face and its two neighbours along the line
         ax = 1 if d == 0 else 0

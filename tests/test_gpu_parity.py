@@ -63,6 +63,18 @@ def test_euler2d_scalar_alpha():
     assert_face_parity(compare_faces(pr, pr.U0, alpha_mode=1))
 
 
+@pytest.mark.parametrize("ct", [1e-4, 1e-3, 0.05, 0.3])
+def test_cutoff_parameter(ct):
+    """A larger C_T narrows the exact all-smooth shortcut; the selection must follow the definition."""
+    _print_case("cutoff", ct)
+    pr = W.euler2d(31, n=96, ny=80)
+    assert_face_parity(compare_faces(pr, pr.U0, ct=ct))
+    pa = W.advection(5, 200)
+    U = pa.U0.copy()
+    U[0, 0, 60:140] += 0.5
+    assert_face_parity(compare_faces(pa, U, ct=ct))
+
+
 @pytest.mark.parametrize("sys", [O.ADV1D, O.EULER1D])
 def test_teno5_faces(sys):
     """TENO5 base scheme (Table 1). Advection keeps the paper's eps = 1e-40. For Euler, eps = 1e-40
