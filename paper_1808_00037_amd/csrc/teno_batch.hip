@@ -1,17 +1,19 @@
 // teno_batch.hip -- many independent Euler problems (1D and 2D, uneven sizes) advanced together.
 //
 // All instances live in one packed state buffer (and packed RK-stage scratch). Each sweep of a
-// stage is one persistent launch over a static work list of (instance, tile) items: block b takes
-// items b, b + G, b + 2G, ... (instance-major order, so concurrently running blocks share an
-// instance's rows in L2). Every instance keeps its own Lax-Friedrichs constants, CFL dt and spread
-// wave-speed maxima. Mode 0 captures the whole nsteps run (per step: 3 x [stage prep, y-sweep of
-// the 2D instances, x-sweep + stage update of all]) in one HIP graph and launches it once; mode 1
-// launches the same kernels once per instance per kernel on the stream. A face or cell is computed
-// by the same code whatever tile or launch holds it, so both modes give bitwise identical states.
+// stage is one launch per system over a static work list of (instance, tile) items, one item per
+// block, with the single-problem kernels' tile code and register budget; the list is instance-major
+// and blocks are renumbered per XCD, so blocks running together on one XCD share an instance's rows
+// in L2. Every instance keeps its own Lax-Friedrichs constants, CFL dt and spread wave-speed
+// maxima. Mode 0 captures the whole nsteps run (per step: 3 x [stage prep, y-sweep of the 2D
+// instances, x-sweep + stage update of the 2D and of the 1D instances]) in one HIP graph and
+// launches it once; mode 1 launches the same kernels once per instance per kernel on the stream. A
+// face or cell is computed by the same code whatever tile or launch holds it, and the maxima are
+// exact, so both modes give bitwise identical states.
 //
-// Tile shapes (segments per x-tile, columns per y-tile) and the persistent grid size are picked by
-// a small autotuner at the first mode-0 run: each candidate advances a scratch copy of the batch by
-// one step (after a warm-up step) and the fastest is kept for the batch.
+// Tile shapes (segments per x-tile, columns per y-tile) are picked by a small autotuner at the
+// first mode-0 run: each candidate advances a scratch copy of the batch by one step (after a
+// warm-up step) and the fastest is kept for the batch.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -32,7 +34,7 @@ using namespace teno;
 
 namespace {
 
-constexpr int NCOPY_B = 8;          // spread copies of the maxima per instance
+constexpr int NCOPY_B = 16;         // spread copies of the maxima per instance
 constexpr int WS_CHUNK = 8192;      // cells per wave-speed work item
 
 struct BatchInst {
@@ -83,13 +85,13 @@ int tiles_y(const teno_grid &g, int nseg_y)
 }  // namespace
 
 // per-item arguments of the plain sweep code
-template <typename T, int DIR>
+template <typename T, int SYS, int DIR>
 __device__ __forceinline__ SweepArgs<T> item_args(const BatchSweep<T> &b, const BatchInst &I, int k)
 {
     SweepArgs<T> a;
     a.U = b.U + I.off;
     a.U0 = b.U0 ? b.U0 + I.off : nullptr;
-    a.addend = (b.addend && I.sys == EULER2D) ? b.addend + I.off : nullptr;
+    a.addend = (b.addend && SYS == EULER2D) ? b.addend + I.off : nullptr;
     a.out = b.out + I.off;
     a.Fout = nullptr;
     a.masks_out = nullptr;
@@ -122,29 +124,31 @@ __device__ __forceinline__ SweepArgs<T> item_args(const BatchSweep<T> &b, const 
     return a;
 }
 
-// y-sweeps produce the y-part of dU/dt (MODE_RHS), x-sweeps apply the RK stage (MODE_STAGE).
-template <typename T, int DIR, int NSEG>
-__global__ void __launch_bounds__(BLOCK, 3) batch_sweep_kernel(BatchSweep<T> b)
+// One (instance, tile) item per block. y-sweeps produce the y-part of dU/dt (MODE_RHS); x-sweeps
+// apply the RK stage (MODE_STAGE) and put the block's wave-speed maxima into one spread copy of the
+// instance's next ring slot. The grid is exactly the item range [begin, end).
+template <typename T, int SYS, int DIR, int NSEG>
+__global__ void __launch_bounds__(BLOCK, SYS == EULER1D ? 3 : (DIR == 0 ? TENO_MIN_WAVES_X : TENO_MIN_WAVES_Y))
+    batch_sweep_kernel(BatchSweep<T> b)
 {
     constexpr int MODE = DIR == 0 ? MODE_STAGE : MODE_RHS;
-    __shared__ T rec[NSEG * seg_stride<EULER2D>()];
-    __shared__ T ext[ext_size<T, EULER2D, DIR, NSEG, MODE>()];
+    __shared__ T rec[NSEG * seg_stride<SYS>()];
+    __shared__ T ext[ext_size<T, SYS, DIR, NSEG, MODE>()];
     __shared__ T coef[NCOEF_ROWS * 8];
     __shared__ double red[BLOCK / WAVE * 9];
+    const Item item = b.items[b.begin + xcd_tile(blockIdx.x, gridDim.x)];
+    const BatchInst I = b.inst[item.inst];
+    const SweepArgs<T> a = item_args<T, SYS, DIR>(b, I, item.inst);
     fill_coef(coef);
-    if (MODE == MODE_STAGE) clear_maxima(red);
-    for (int it = b.begin + (int)blockIdx.x; it < b.end; it += (int)gridDim.x) {
-        const Item item = b.items[it];
-        const BatchInst I = b.inst[item.inst];
-        SweepArgs<T> a = item_args<T, DIR>(b, I, item.inst);
-        if (I.sys == EULER2D) sweep_tile<T, EULER2D, DIR, false, NSEG, MODE>(a, item.tile, rec, ext, coef, red);
-        else if (DIR == 0) sweep_tile<T, EULER1D, 0, false, NSEG, MODE>(a, item.tile, rec, ext, coef, red);
-        __syncthreads();              // the next item restages the LDS tile
-        if (MODE == MODE_STAGE) {
-            // flush the maxima when the block's next item belongs to another instance (or none)
-            const int nxt = it + (int)gridDim.x;
-            if (nxt >= b.end || b.items[nxt].inst != item.inst)
-                flush_maxima(red, &b.ictrl[item.inst].part[b.ring_next][blockIdx.x % NCOPY_B][0]);
+    if (MODE == MODE_STAGE && threadIdx.x < BLOCK / WAVE * 9) red[threadIdx.x] = 0.0;   // ordered by the
+    sweep_tile<T, SYS, DIR, false, NSEG, MODE>(a, item.tile, rec, ext, coef, red);        // staging barrier
+    if (MODE == MODE_STAGE) {
+        __syncthreads();
+        if (threadIdx.x < 9) {
+            double m = 0.0;
+            for (int q = 0; q < BLOCK / WAVE; ++q) m = fmax(m, red[q * 9 + threadIdx.x]);
+            atomicMax(&b.ictrl[item.inst].part[b.ring_next][blockIdx.x % NCOPY_B][threadIdx.x],
+                      (unsigned long long)__double_as_longlong(m));
         }
     }
 }
@@ -232,15 +236,16 @@ struct teno_batch {
     InstCtrl *ictrl_d = nullptr;
     unsigned *err_d = nullptr;
     void *S1 = nullptr, *S2 = nullptr, *dUy = nullptr;
-    // work lists, one per tile-shape variant (index 0: 4 segments, 1: 8 segments per tile)
+    // work lists, one per tile-shape variant (index 0: 4 segments, 1: 8 segments per tile). The
+    // x-list holds the 2D instances' items first (ending at x2_end), then the 1D instances'.
     Item *items_x_d[2] = {nullptr, nullptr}, *items_y_d[2] = {nullptr, nullptr};
-    std::vector<int> begin_x[2], begin_y[2];          // per-instance item ranges (n + 1 entries)
+    std::vector<int> xb[2], xe[2], yb[2], ye[2];      // per-instance item ranges
+    int x2_end[2] = {0, 0}, x_total[2] = {0, 0}, y_total[2] = {0, 0};
     Item *items_w_d = nullptr;
     std::vector<int> begin_w;
     // tuned launch shape
     bool tuned = false;
-    int vx = 0, vy = 1, blocks_per_cu = 3;
-    int num_cu = 256;
+    int vx = 0, vy = 1;
     // captured run
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
@@ -267,54 +272,70 @@ BatchSweep<T> base_args(const teno_batch *b)
     return a;
 }
 
-template <typename T, int DIR>
-void launch_batch_sweep(teno_batch *b, hipStream_t s, int variant, BatchSweep<T> a, int grid)
+template <typename T, int SYS, int DIR>
+void launch_batch_sweep(hipStream_t s, int variant, const BatchSweep<T> &a)
 {
-    if (a.end <= a.begin) return;
+    const int grid = a.end - a.begin;
+    if (grid <= 0) return;
     if (variant == 0)
-        hipLaunchKernelGGL((batch_sweep_kernel<T, DIR, 4>), dim3(grid), dim3(BLOCK), 0, s, a);
+        hipLaunchKernelGGL((batch_sweep_kernel<T, SYS, DIR, 4>), dim3(grid), dim3(BLOCK), 0, s, a);
     else
-        hipLaunchKernelGGL((batch_sweep_kernel<T, DIR, 8>), dim3(grid), dim3(BLOCK), 0, s, a);
+        hipLaunchKernelGGL((batch_sweep_kernel<T, SYS, DIR, 8>), dim3(grid), dim3(BLOCK), 0, s, a);
 }
 
-int persistent_grid(const teno_batch *b, int nitems)
+// Item ranges of one launch group: y-items, 2D x-items, 1D x-items.
+struct Ranges {
+    int y0, y1, x2a, x2b, x1a, x1b;
+};
+
+Ranges all_ranges(const teno_batch *b, int vx, int vy)
 {
-    int g = b->num_cu * b->blocks_per_cu;
-    return nitems < g ? (nitems > 0 ? nitems : 1) : g;
+    return {0, b->y_total[vy], 0, b->x2_end[vx], b->x2_end[vx], b->x_total[vx]};
 }
 
-// Enqueue one SSP-RK3 step of the instances [first, last) (mode 0: all in one launch per kernel).
+Ranges instance_ranges(const teno_batch *b, int k, int vx, int vy)
+{
+    Ranges r{b->yb[vy][k], b->ye[vy][k], 0, 0, 0, 0};
+    if (b->inst[k].sys == EULER2D) {
+        r.x2a = b->xb[vx][k];
+        r.x2b = b->xe[vx][k];
+    } else {
+        r.x1a = b->xb[vx][k];
+        r.x1b = b->xe[vx][k];
+    }
+    return r;
+}
+
+// Enqueue one SSP-RK3 step of the instances [first, first + count) whose items are r.
 template <typename T>
-void enqueue_step_range(teno_batch *b, hipStream_t s, T *U, int first, int last, bool per_instance_grid,
-                        int vx, int vy)
+void enqueue_step(teno_batch *b, hipStream_t s, T *U, int first, int count, const Ranges &r, int vx, int vy)
 {
     T *in[3] = {U, (T *)b->S1, (T *)b->S2};
     T *outp[3] = {(T *)b->S1, (T *)b->S2, U};
     for (int k = 0; k < 3; ++k) {
-        const int cnt = last - first;
-        hipLaunchKernelGGL(batch_prep_kernel, dim3(cnt < 1024 ? cnt : 1024), dim3(64), 0, s, b->ictrl_d, first, cnt,
-                           k, k, b->opts.cfl, b->err_d);
+        hipLaunchKernelGGL(batch_prep_kernel, dim3(count < 1024 ? count : 1024), dim3(64), 0, s, b->ictrl_d, first,
+                           count, k, k, b->opts.cfl, b->err_d);
         BatchSweep<T> a = base_args<T>(b);
         a.stage = k;
         a.U = in[k];
         a.items = b->items_y_d[vy];
-        a.begin = b->begin_y[vy][first];
-        a.end = b->begin_y[vy][last];
+        a.begin = r.y0;
+        a.end = r.y1;
         a.mode = MODE_RHS;
         a.out = (T *)b->dUy;
-        int ny_items = a.end - a.begin;
-        launch_batch_sweep<T, 1>(b, s, vy, a, per_instance_grid ? (ny_items > 0 ? ny_items : 1)
-                                                                : persistent_grid(b, ny_items));
+        launch_batch_sweep<T, EULER2D, 1>(s, vy, a);
         a.items = b->items_x_d[vx];
-        a.begin = b->begin_x[vx][first];
-        a.end = b->begin_x[vx][last];
         a.mode = MODE_STAGE;
         a.U0 = U;
         a.addend = (T *)b->dUy;
         a.out = outp[k];
         a.ring_next = (k + 1) % 3;
-        int nx_items = a.end - a.begin;
-        launch_batch_sweep<T, 0>(b, s, vx, a, per_instance_grid ? nx_items : persistent_grid(b, nx_items));
+        a.begin = r.x2a;
+        a.end = r.x2b;
+        launch_batch_sweep<T, EULER2D, 0>(s, vx, a);
+        a.begin = r.x1a;
+        a.end = r.x1b;
+        launch_batch_sweep<T, EULER1D, 0>(s, vx, a);
     }
 }
 
@@ -336,11 +357,12 @@ teno_status run_t(teno_batch *b, T *U, int nsteps, int mode)
         // one launch per instance per kernel, plain stream launches
         enqueue_init<T>(b, b->stream, U, 0, b->n);
         for (int n = 0; n < nsteps; ++n)
-            for (int k = 0; k < b->n; ++k) enqueue_step_range<T>(b, b->stream, U, k, k + 1, true, 0, 1);
+            for (int k = 0; k < b->n; ++k)
+                enqueue_step<T>(b, b->stream, U, k, 1, instance_ranges(b, k, 0, 1), 0, 1);
         return hipGetLastError() == hipSuccess ? TENO_OK : TENO_E_HIP;
     }
     if (!b->tuned) {
-        // autotune on a scratch copy of the batch: candidates (x-tile, y-tile, blocks per CU)
+        // autotune on a scratch copy of the batch: candidates (x-tile, y-tile)
         T *tmp = nullptr;
         HIP_TRY(hipMalloc(&tmp, b->total * sizeof(T)));
         HIP_TRY(hipMemcpyAsync(tmp, U, b->total * sizeof(T), hipMemcpyDeviceToDevice, b->stream));
@@ -348,28 +370,25 @@ teno_status run_t(teno_batch *b, T *U, int nsteps, int mode)
         HIP_TRY(hipEventCreate(&e0));
         HIP_TRY(hipEventCreate(&e1));
         float best = 1e30f;
-        int bvx = 0, bvy = 1, bbpc = 3;
-        const int bpcs[3] = {2, 3, 4};
+        int bvx = 0, bvy = 1;
         for (int vx = 0; vx < 2; ++vx)
-            for (int vy = 0; vy < 2; ++vy)
-                for (int bi = 0; bi < 3; ++bi) {
-                    b->blocks_per_cu = bpcs[bi];
-                    enqueue_init<T>(b, b->stream, tmp, 0, b->n);
-                    enqueue_step_range<T>(b, b->stream, tmp, 0, b->n, false, vx, vy);    // warm-up
-                    HIP_TRY(hipEventRecord(e0, b->stream));
-                    enqueue_step_range<T>(b, b->stream, tmp, 0, b->n, false, vx, vy);
-                    HIP_TRY(hipEventRecord(e1, b->stream));
-                    HIP_TRY(hipEventSynchronize(e1));
-                    float ms = 0.f;
-                    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-                    if (ms < best) { best = ms; bvx = vx; bvy = vy; bbpc = bpcs[bi]; }
-                }
+            for (int vy = 0; vy < 2; ++vy) {
+                const Ranges r = all_ranges(b, vx, vy);
+                enqueue_init<T>(b, b->stream, tmp, 0, b->n);
+                enqueue_step<T>(b, b->stream, tmp, 0, b->n, r, vx, vy);    // warm-up
+                HIP_TRY(hipEventRecord(e0, b->stream));
+                enqueue_step<T>(b, b->stream, tmp, 0, b->n, r, vx, vy);
+                HIP_TRY(hipEventRecord(e1, b->stream));
+                HIP_TRY(hipEventSynchronize(e1));
+                float ms = 0.f;
+                HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+                if (ms < best) { best = ms; bvx = vx; bvy = vy; }
+            }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         HIP_TRY(hipFree(tmp));
         b->vx = bvx;
         b->vy = bvy;
-        b->blocks_per_cu = bbpc;
         b->tuned = true;
         unsigned z = 0;     // the tuning run's state is discarded, and so is its status
         HIP_TRY(hipMemcpy(b->err_d, &z, sizeof z, hipMemcpyHostToDevice));
@@ -382,7 +401,8 @@ teno_status run_t(teno_batch *b, T *U, int nsteps, int mode)
         if (!b->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
         HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
         enqueue_init<T>(b, b->cap_stream, U, 0, b->n);
-        for (int n = 0; n < nsteps; ++n) enqueue_step_range<T>(b, b->cap_stream, U, 0, b->n, false, b->vx, b->vy);
+        const Ranges r = all_ranges(b, b->vx, b->vy);
+        for (int n = 0; n < nsteps; ++n) enqueue_step<T>(b, b->cap_stream, U, 0, b->n, r, b->vx, b->vy);
         HIP_TRY(hipStreamEndCapture(b->cap_stream, &b->graph));
         HIP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
         b->graph_U = U;
@@ -444,36 +464,41 @@ teno_status teno_batch_create(const teno_grid *grids, int32_t n, const teno_opts
         off += (ne + 63) / 64 * 64;                       // 512-byte aligned instances (FP64)
     }
     b->total = off;
-    int dev = 0;
     teno_status st = TENO_OK;
-    if (hipGetDevice(&dev) == hipSuccess) {
-        int cu = 0;
-        if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cu > 0)
-            b->num_cu = cu;
-    }
-    // work lists
+    // work lists: x-items of the 2D instances, then of the 1D ones; y-items of the 2D instances
     std::vector<Item> it;
     for (int v = 0; v < 2; ++v) {
         const int ns = v == 0 ? 4 : 8;
+        b->xb[v].assign(n, 0);
+        b->xe[v].assign(n, 0);
+        b->yb[v].assign(n, 0);
+        b->ye[v].assign(n, 0);
         it.clear();
-        b->begin_x[v].assign(1, 0);
-        for (int k = 0; k < n; ++k) {
-            int t = tiles_x(grids[k], ns);
-            for (int q = 0; q < t; ++q) it.push_back({k, q});
-            b->begin_x[v].push_back((int)it.size());
+        for (int pass = 0; pass < 2; ++pass) {
+            for (int k = 0; k < n; ++k) {
+                if ((grids[k].sys == TENO_EULER2D) != (pass == 0)) continue;
+                b->xb[v][k] = (int)it.size();
+                int t = tiles_x(grids[k], ns);
+                for (int q = 0; q < t; ++q) it.push_back({k, q});
+                b->xe[v][k] = (int)it.size();
+            }
+            if (pass == 0) b->x2_end[v] = (int)it.size();
         }
-        if (hipMalloc(&b->items_x_d[v], it.size() * sizeof(Item)) != hipSuccess ||
-            hipMemcpy(b->items_x_d[v], it.data(), it.size() * sizeof(Item), hipMemcpyHostToDevice) != hipSuccess)
+        b->x_total[v] = (int)it.size();
+        if (hipMalloc(&b->items_x_d[v], (it.size() + 1) * sizeof(Item)) != hipSuccess ||
+            (it.size() && hipMemcpy(b->items_x_d[v], it.data(), it.size() * sizeof(Item), hipMemcpyHostToDevice) !=
+                              hipSuccess))
             st = TENO_E_HIP;
         it.clear();
-        b->begin_y[v].assign(1, 0);
         for (int k = 0; k < n; ++k) {
+            b->yb[v][k] = (int)it.size();
             if (grids[k].sys == TENO_EULER2D) {
                 int t = tiles_y(grids[k], ns);
                 for (int q = 0; q < t; ++q) it.push_back({k, q});
             }
-            b->begin_y[v].push_back((int)it.size());
+            b->ye[v][k] = (int)it.size();
         }
+        b->y_total[v] = (int)it.size();
         if (hipMalloc(&b->items_y_d[v], (it.size() + 1) * sizeof(Item)) != hipSuccess ||
             (it.size() && hipMemcpy(b->items_y_d[v], it.data(), it.size() * sizeof(Item), hipMemcpyHostToDevice) !=
                               hipSuccess))
