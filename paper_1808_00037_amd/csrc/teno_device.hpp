@@ -85,6 +85,13 @@ __device__ __forceinline__ int bc_index(int i, int n, int bc)
     return i < 0 ? 0 : (i >= n ? n - 1 : i);
 }
 
+// bc_index for -n <= i < 2n (one wrap at most, no division).
+__device__ __forceinline__ int bc_index_near(int i, int n, int bc)
+{
+    if (bc == 0) return i < 0 ? i + n : (i >= n ? i - n : i);
+    return i < 0 ? 0 : (i >= n ? n - 1 : i);
+}
+
 // ------------------------------------------------------------------------------------------------
 // Reconstruction coefficients. Rows 0..12: Table 2 (a_{m,l}, l = i-3..i+3). Rows 13..19: Table 1
 // (TENO5 single polynomials, l = i-2..i+2 placed in columns 1..5). Exact rationals; each entry is
@@ -228,6 +235,36 @@ __device__ __forceinline__ double recip(double x)
     return fma(r, e, r);
 }
 __device__ __forceinline__ float recip(float x) { return 1.0f / x; }
+
+// Square root and reciprocal square root of a normal positive double: the hardware estimate
+// y ~ 1/sqrt(x), then coupled Newton steps on g ~ sqrt(x) and h ~ 1/(2 sqrt(x)) (each step squares
+// the relative error), ending with a residual correction of g. Within about an ulp of the correctly
+// rounded values; non-positive or non-finite x give NaN or infinities.
+__device__ __forceinline__ void sqrt_rsqrt(double x, double &s, double &rs)
+{
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y, h = 0.5 * y;
+    double r = fma(-h, g, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    r = fma(-h, g, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    const double d = fma(-g, g, x);
+    s = fma(d, h, g);
+    rs = 2.0 * h;
+}
+__device__ __forceinline__ void sqrt_rsqrt(float x, float &s, float &rs)
+{
+    s = sqrtf(x);
+    rs = 1.0f / s;
+}
+template <typename T> __device__ __forceinline__ T fast_sqrt(T x)
+{
+    T s, rs;
+    sqrt_rsqrt(x, s, rs);
+    return s;
+}
 
 __device__ __forceinline__ unsigned cutoff3(const Smooth<double> &m, double eps, double ct)
 {
@@ -395,11 +432,11 @@ __device__ __forceinline__ bool cell_primitive_speeds(const T *u, T gamma, T gm1
     } else {
         constexpr int NV = Sys<SYS>::NV;
         T rho = u[0], mx = u[1], my = NV == 4 ? u[2] : T(0), E = u[NV - 1];
-        T ir = rho > T(0) ? recip(rho) : T(1) / rho;
+        T ir = recip(rho);
         T vx = mx * ir, vy = my * ir;
         T p = gm1 * (E - T(0.5) * rho * (vx * vx + vy * vy));
         bool ok = rho > T(0) && p > T(0) && isfinite(E);
-        sc = (double)sqrt(gamma * p * ir);
+        sc = (double)fast_sqrt(gamma * p * ir);
         sx = (double)vx;
         sy = (double)vy;
         return ok;
@@ -535,17 +572,14 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
         }
     };
 
-    // ---- stage cells into LDS (coalesced along x in both sweeps) ----
+    // ---- stage cells into LDS ----
+    // x-sweeps: each wave stages its own segments (runs of SEG_LOAD cells of a row: coalesced, and
+    // the index arithmetic is wave-uniform). y-sweeps: the block stages its NSEG adjacent columns
+    // row by row, so that one global load reads NSEG consecutive doubles of a row. A staged run
+    // spans cells c0-5 .. c0+66 with c0 < len, so for len >= SEG_LOAD one wrap suffices.
     unsigned bad = 0;
-    for (int idx = tid; idx < NSEG * SEG_LOAD; idx += BLOCK) {
-        int s, q;
-        if (DIR == 0) { s = idx / SEG_LOAD; q = idx % SEG_LOAD; }
-        else          { s = idx % NSEG;     q = idx / NSEG; }
-        int line, c0;
-        seg_of(s, line, c0);
-        if (line < 0) continue;
-        int g = bc_index(c0 - SEG_HALO + q, a.len, a.bc);
-        size_t off = DIR == 0 ? (size_t)line * a.nx + g : (size_t)g * a.nx + line;
+    const bool near = a.len >= SEG_LOAD;
+    auto stage_cell = [&](int s, int q, size_t off) {
         T *r = rec + s * SEG_STRIDE + q;
         if constexpr (!EULER) {
             r[0] = a.U[off];
@@ -555,7 +589,10 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
             T mn = a.U[(size_t)gvar<SYS, DIR>(1) * ncell + off];
             T mt = NV == 4 ? a.U[(size_t)gvar<SYS, DIR>(2) * ncell + off] : T(0);
             T E = a.U[(size_t)(NV - 1) * ncell + off];
-            T ir = T(1) / rho;
+            T sq, ir;
+            sqrt_rsqrt(rho, sq, ir);
+            ir = ir * ir;
+            if (!(rho > T(0))) ir = T(1) / rho;
             T un = mn * ir, ut = mt * ir;
             T p = a.gm1 * (E - T(0.5) * rho * (un * un + ut * ut));
             if (!(rho > T(0) && p > T(0))) bad |= (isfinite(rho) && isfinite(p)) ? ERR_NONPHYSICAL : ERR_NONFINITE;
@@ -566,31 +603,50 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
             r[SEG_LOAD * S::UN] = un;
             if constexpr (NV == 4) r[SEG_LOAD * S::UT] = ut;
             r[SEG_LOAD * S::P] = p;
-            r[SEG_LOAD * S::S] = sqrt(rho);
+            r[SEG_LOAD * S::S] = sq;
             r[SEG_LOAD * S::H] = (E + p) * ir;
         }
-    }
+    };
     // epilogue operands of the owned cells (lanes 1..61), staged with the tile so that their
     // latency overlaps the staging instead of the end of the face computation
     constexpr bool HAS_EXT = DIR == 0 && MODE != MODE_FACES;
-    if constexpr (HAS_EXT) {
-        const bool want0 = MODE == MODE_STAGE, want1 = a.addend != nullptr;
-        if (want0 || want1) {
-            for (int idx = tid; idx < NSEG * SEG_CELLS; idx += BLOCK) {
-                const int s = idx / SEG_CELLS, kk = idx % SEG_CELLS + 1;
-                int line, c0;
-                seg_of(s, line, c0);
-                const int c = c0 - 1 + kk;
-                if (line < 0 || c >= a.len) continue;
-                const size_t off = (size_t)line * a.nx + c;
-                T *e = ext + (size_t)s * 2 * NV * WAVE + kk;
+    if constexpr (DIR == 0) {
+        for (int s = __builtin_amdgcn_readfirstlane(wid); s < NSEG; s += BLOCK / WAVE) {
+            int line, c0;
+            seg_of(s, line, c0);
+            if (line < 0) continue;             // wave-uniform
+            const size_t lbase = (size_t)line * a.nx;
+            for (int q = lane; q < SEG_LOAD; q += WAVE) {
+                const int g = near ? bc_index_near(c0 - SEG_HALO + q, a.len, a.bc)
+                                   : bc_index(c0 - SEG_HALO + q, a.len, a.bc);
+                stage_cell(s, q, lbase + g);
+            }
+            if constexpr (HAS_EXT) {
+                const bool want0 = MODE == MODE_STAGE, want1 = a.addend != nullptr;
+                const int c = c0 - 1 + lane;
+                if ((want0 || want1) && lane >= 1 && lane <= SEG_CELLS && c < a.len) {
+                    const size_t off = lbase + c;
+                    T *e = ext + (size_t)s * 2 * NV * WAVE + lane;
 #pragma unroll
-                for (int v = 0; v < NV; ++v) {
-                    const size_t go = (size_t)gvar<SYS, DIR>(v) * ncell + off;
-                    if (want0) e[v * WAVE] = a.U0[go];
-                    if (want1) e[(NV + v) * WAVE] = a.addend[go];
+                    for (int v = 0; v < NV; ++v) {
+                        const size_t go = (size_t)gvar<SYS, DIR>(v) * ncell + off;
+                        if (want0) e[v * WAVE] = a.U0[go];
+                        if (want1) e[(NV + v) * WAVE] = a.addend[go];
+                    }
                 }
             }
+        }
+    } else {
+        static_assert(DIR == 0 || (NSEG & (NSEG - 1)) == 0, "y-tiles hold a power-of-two number of columns");
+        const int ntile = (a.nlines + NSEG - 1) / NSEG;
+        const int line0 = (tile % ntile) * NSEG, c0 = (tile / ntile) * SEG_CELLS;
+        for (int idx = tid; idx < NSEG * SEG_LOAD; idx += BLOCK) {
+            const int s = idx % NSEG, q = idx / NSEG;
+            const int line = line0 + s;
+            if (line >= a.nlines) continue;
+            const int g = near ? bc_index_near(c0 - SEG_HALO + q, a.len, a.bc)
+                               : bc_index(c0 - SEG_HALO + q, a.len, a.bc);
+            stage_cell(s, q, (size_t)g * a.nx + line);
         }
     }
     __syncthreads();
@@ -628,7 +684,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
             using S = Sys<SYS>;
             const T gm1 = a.gm1;
             T sL = R0[SEG_LOAD * S::S + k + 3], sR = R0[SEG_LOAD * S::S + k + 4];
-            T isum = T(1) / (sL + sR);
+            T isum = recip(sL + sR);
             roe.un = (sL * R0[SEG_LOAD * S::UN + k + 3] + sR * R0[SEG_LOAD * S::UN + k + 4]) * isum;
             roe.ut = T(0);
             if constexpr (NV == 4)
@@ -637,8 +693,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
             roe.q2 = roe.un * roe.un + roe.ut * roe.ut;
             T c2 = gm1 * (roe.H - T(0.5) * roe.q2);
             if (face_ok && !(c2 > T(0))) bad |= isfinite(c2) ? ERR_NONPHYSICAL : ERR_NONFINITE;
-            roe.cs = sqrt(c2);
-            roe.ic = T(1) / roe.cs;
+            sqrt_rsqrt(c2, roe.cs, roe.ic);
             roe.b1 = gm1 * roe.ic * roe.ic;
             roe.b2 = T(0.5) * roe.b1 * roe.q2;
         }
