@@ -93,6 +93,35 @@ def advection_exact(problem, t):
 
 
 # ------------------------------------------------------------------------------------------------
+# Inviscid Burgers: u_t + (u^2/2)_x = 0 on [0, 2), periodic, u0 = 1/2 + sin(pi (x - shift)) (the
+# paper's case at shift = 0; smooth until t = 1/pi, then a shock forms).
+# ------------------------------------------------------------------------------------------------
+def burgers_wave(x, shift=0.0):
+    return 0.5 + np.sin(np.pi * (x - shift))
+
+
+def burgers(n, cfl=0.5, t_end=0.5 / math.pi, shift=0.0):
+    x = cell_centres(0.0, 2.0, n)
+    U0 = burgers_wave(x, shift)[None, None, :].astype(np.float64)
+    return Problem("burgers", BURGERS1D, n, 1, 0.0, 2.0, 0.0, 1.0, PERIODIC, PERIODIC, U0, cfl=cfl,
+                   meta=dict(t_end=t_end, shift=shift))
+
+
+def burgers_exact(problem, t, iters=60):
+    """Smooth solution (t < 1/pi) by characteristics: u = u0(x - u t), solved by Newton's method
+    started from u0(x) (the map is a contraction-free monotone root problem for t < 1/pi)."""
+    x = cell_centres(problem.x0, problem.x1, problem.nx)
+    shift = problem.meta.get("shift", 0.0)
+    u = burgers_wave(x, shift)
+    for _ in range(iters):
+        ph = np.pi * (x - u * t - shift)
+        g = u - 0.5 - np.sin(ph)
+        dg = 1.0 + np.pi * t * np.cos(ph)
+        u = u - g / dg
+    return u
+
+
+# ------------------------------------------------------------------------------------------------
 # One-dimensional Euler: Riemann state with a sinusoidal density perturbation on the right.
 # [0, 10], interface at x = 1, outflow boundaries.
 # ------------------------------------------------------------------------------------------------

@@ -26,6 +26,11 @@ def _case(name):
         U = pr.U0.copy()
         U[0, 0, 18:] += 0.8
         return pr, U
+    if name == "bu":
+        pr = W.burgers(48, shift=0.2)
+        U = pr.U0.copy()
+        U[0, 0, 30:] -= 0.7          # a step: some stencils cut
+        return pr, U
     if name == "e1o":
         pr = W.euler1d(4, n=30)
         pr.x1 = 1.0
@@ -53,7 +58,7 @@ def _frozen_inputs(pr, U):
     return cfg, ex, masks
 
 
-@pytest.mark.parametrize("name", ["adv", "e1o", "e1p", "e2p", "e2o"])
+@pytest.mark.parametrize("name", ["adv", "bu", "e1o", "e1p", "e2p", "e2o"])
 def test_rhs_vjp_elementwise(name):
     pr, U = _case(name)
     print("[case] rhs_vjp", name, flush=True)

@@ -63,6 +63,37 @@ def test_euler2d_scalar_alpha():
     assert_face_parity(compare_faces(pr, pr.U0, alpha_mode=1))
 
 
+def _burgers_shocked(n):
+    """Burgers state after the shock has formed (t = 1.5/pi), computed by the oracle alone."""
+    import math
+    pr = W.burgers(n)
+    t_end = 1.5 / math.pi
+    nsteps = int(math.ceil(t_end / (0.4 * pr.dx / 1.5)))
+    U = O.run(oracle_cfg(pr), pr.U0, nsteps, dt=t_end / nsteps)
+    return pr, U
+
+
+@pytest.mark.parametrize("n", [61, 160, 1000])
+def test_burgers_faces(n):
+    _print_case("burgers", n)
+    pr = W.burgers(n, shift=0.1)
+    assert_face_parity(compare_faces(pr, pr.U0))
+    pr, U = _burgers_shocked(n)
+    assert_face_parity(compare_faces(pr, U))
+
+
+def test_burgers_steps_through_a_shock():
+    pr, U0 = _burgers_shocked(200)
+    cfg = oracle_cfg(pr)
+    Uo = O.run(cfg, U0, 10, dt=0.0, cfl=pr.cfl)
+    sv = solver_for(pr)
+    U = torch.from_numpy(U0.copy()).cuda()
+    sv.run(U, 10, dt=0.0, graph=True)
+    sv.poll()
+    err = np.abs(U.cpu().numpy() - Uo).max() / np.abs(Uo).max()
+    assert err < 1e-11, err
+
+
 @pytest.mark.parametrize("ct", [1e-4, 1e-3, 0.05, 0.3])
 def test_cutoff_parameter(ct):
     """A larger C_T narrows the exact all-smooth shortcut; the selection must follow the definition."""
