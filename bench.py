@@ -192,6 +192,35 @@ def adjoint_cost(n=1024, nsteps=400, ckpt=20, seed=21):
             "ms_backward": t_bwd, "bwd_over_fwd": t_bwd / t_fwd, "fd_rel_err_2dirs": worst}
 
 
+def scheme_cost(n=4096, steps=10, seed=1):
+    """The paper's efficiency claim, quantified: SSP-RK3 step time of TENO7X and of its TENO5 base
+    (Table 1, eps = 1e-40) on the same 2D Euler state, same kernels apart from the selection."""
+    import torch
+    from paper_1808_00037_amd import teno as T
+    from paper_1808_00037_amd import workloads as W
+
+    pr = W.euler2d(seed, n=n)
+    res = {}
+    for name, scheme in (("teno7x", T.TENO7X), ("teno5", T.TENO5)):
+        sv = T.Solver.for_problem(pr, scheme=scheme)
+        U = torch.from_numpy(pr.U0).cuda()
+        sv.run(U, 2, graph=True)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        sv.run(U, steps, graph=True)
+        e1.record()
+        torch.cuda.synchronize()
+        sv.poll()
+        res[f"ms_per_step_{name}"] = e0.elapsed_time(e1) / steps
+        del sv, U
+        torch.cuda.empty_cache()
+    res["teno7x_over_teno5"] = res["ms_per_step_teno7x"] / res["ms_per_step_teno5"]
+    res["n"] = n
+    res["steps"] = steps
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -292,6 +321,10 @@ def main():
         log("batched vs one launch per instance (512 instances)")
         out["batched"] = batched_speedup()
         log(json.dumps(out["batched"]))
+        torch.cuda.empty_cache()
+        log("TENO7X vs TENO5 step cost")
+        out["scheme_cost"] = scheme_cost(n=n)
+        log(json.dumps(out["scheme_cost"]))
         torch.cuda.empty_cache()
         log("adjoint cost (1024^2, 400 steps, checkpoints every 20)")
         out["adjoint"] = adjoint_cost()

@@ -126,17 +126,35 @@ __device__ constexpr Rat COEF[NCOEF_ROWS][7] = {
 // (at least one chi_k >= 1/3 > C_T); it maps to the full stencil and is reported as an error.
 __device__ constexpr int TENO5_ROW[8] = {13, 16, 17, 14, 18, 19, 15, 13};
 
-// Table 2 row 0 applied to seven upwind-ordered values, constants folded at compile time.
-template <typename T>
-__device__ __forceinline__ T recon_row0(T w0, T w1, T w2, T w3, T w4, T w5, T w6)
+// Row R of the coefficient table applied to seven upwind-ordered values, with the constants folded
+// at compile time (each the correctly rounded quotient in T) and the zero taps dropped; the sum
+// runs left to right like the table-driven path.
+template <typename T, int R, int L>
+__device__ __forceinline__ void recon_tap(T &h, bool &first, T w)
 {
-    T h = T(-1.0 / 140.0) * w0;
-    h += T(5.0 / 84.0) * w1;
-    h += T(-101.0 / 420.0) * w2;
-    h += T(319.0 / 420.0) * w3;
-    h += T(107.0 / 210.0) * w4;
-    h += T(-19.0 / 210.0) * w5;
-    h += T(1.0 / 105.0) * w6;
+    if constexpr (COEF[R][L].n != 0) {
+        constexpr T c = T(COEF[R][L].n) / T(COEF[R][L].d);
+        if (first) {
+            h = c * w;
+            first = false;
+        } else {
+            h += c * w;
+        }
+    }
+}
+
+template <typename T, int R>
+__device__ __forceinline__ T recon_const(T w0, T w1, T w2, T w3, T w4, T w5, T w6)
+{
+    T h = T(0);
+    bool first = true;
+    recon_tap<T, R, 0>(h, first, w0);
+    recon_tap<T, R, 1>(h, first, w1);
+    recon_tap<T, R, 2>(h, first, w2);
+    recon_tap<T, R, 3>(h, first, w3);
+    recon_tap<T, R, 4>(h, first, w4);
+    recon_tap<T, R, 5>(h, first, w5);
+    recon_tap<T, R, 6>(h, first, w6);
     return h;
 }
 
@@ -793,8 +811,12 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
             T hp, hm;
             if (__all(mp == 0 && mm == 0)) {
                 // Table 2 row 0 (the seventh-order linear scheme) as compile-time constants
-                hp = recon_row0<T>(vp[0], vp[1], vp[2], vp[3], vp[4], vp[5], vp[6]);
-                hm = recon_row0<T>(vm[7], vm[6], vm[5], vm[4], vm[3], vm[2], vm[1]);
+                hp = recon_const<T, 0>(vp[0], vp[1], vp[2], vp[3], vp[4], vp[5], vp[6]);
+                hm = recon_const<T, 0>(vm[7], vm[6], vm[5], vm[4], vm[3], vm[2], vm[1]);
+            } else if (a.scheme == 1 && __all(mp == TENO5_ROW[7] && mm == TENO5_ROW[7])) {
+                // TENO5 with every flag kept: its fifth-order linear scheme (Table 1, 111)
+                hp = recon_const<T, TENO5_ROW[7]>(vp[0], vp[1], vp[2], vp[3], vp[4], vp[5], vp[6]);
+                hm = recon_const<T, TENO5_ROW[7]>(vm[7], vm[6], vm[5], vm[4], vm[3], vm[2], vm[1]);
             } else {
                 const T *cp_ = coef + mp * 8;
                 const T *cm_ = coef + mm * 8;
