@@ -1,0 +1,100 @@
+"""Parity at the benchmark's full size: 2D Euler 4096 x 4096 FP64, periodic, through the C ABI in
+the launch configuration the benchmark times.
+
+The oracle cannot evaluate the whole operator quickly at this size, so it is checked on samples it
+can compute one by one: the cell's derivative depends on the cells within five of it along its row
+and column and on the domain-wide Lax-Friedrichs constants. The oracle computes those constants on
+the full state itself, then evaluates each sampled cell on a 17 x 17 window centred on it (outflow
+padding never reaches the centre). Whole-state properties cover the rest: conservation of the
+periodic step and the CFL time step against the oracle's wave speeds.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_1808_00037_amd import teno as T
+from paper_1808_00037_amd import workloads as W
+
+from gpu_common import oracle_cfg, solver_for
+
+pytestmark = pytest.mark.gpu
+
+N = 4096
+HW = 8          # window half-width
+
+
+@pytest.fixture(scope="module")
+def problem():
+    return W.euler2d(1, n=N)
+
+
+def _samples(pr, rng):
+    n = pr.nx
+    pts = [tuple(p) for p in rng.integers(0, n, size=(800, 2))]
+    # the quadrant interfaces, the periodic seams and the vortex
+    for k in rng.integers(0, n, size=100):
+        pts += [(n // 2 - 1, k), (n // 2, k), (k, n // 2 - 1), (k, n // 2), (0, k), (n - 1, k), (k, 0), (k, n - 1)]
+    xc, yc = pr.meta["centre"]
+    cx, cy = int(xc * n), int(yc * n)
+    for d in rng.integers(-300, 300, size=(200, 2)):
+        pts.append(((cy + d[0]) % n, (cx + d[1]) % n))
+    return sorted(set(pts))
+
+
+def _window(pr, j, i):
+    n = pr.nx
+    rows = (np.arange(j - HW, j + HW + 1)) % n
+    cols = (np.arange(i - HW, i + HW + 1)) % n
+    return np.ascontiguousarray(pr.U0[:, rows][:, :, cols])
+
+
+def test_rhs_samples_at_full_size(problem):
+    pr = problem
+    print("[case] full-size rhs", flush=True)
+    sv = solver_for(pr)
+    g = sv.rhs(torch.from_numpy(pr.U0).cuda()).cpu().numpy()
+    sv.poll()
+    alpha, _ = O.wave_speeds(oracle_cfg(pr), pr.U0)
+    w = 2 * HW + 1
+    wcfg = O.Config(O.EULER2D, w, w, 0.0, w * pr.dx, 0.0, w * pr.dy, O.OUTFLOW, O.OUTFLOW)
+    rng = np.random.default_rng(11)
+    pts = _samples(pr, rng)
+    h = pr.dx
+    bad = []
+    near_ct = 0
+    for (j, i) in pts:
+        Uw = _window(pr, j, i)
+        ro, ex = O.rhs(wcfg, Uw, alpha=alpha, want_faces=True)
+        o = ro[:, HW, HW]
+        scale = max(np.abs(Uw).max(), 1.0)
+        err = np.abs(g[:, j, i] - o).max() * h / scale
+        if err > 4e-12:
+            # accepted only where a cut-off decision of the cell's faces sits within rounding of C_T
+            chis = np.concatenate([ex["chi_x"][HW, HW:HW + 2].ravel(), ex["chi_y"][HW:HW + 2, HW].ravel()])
+            if np.any(np.abs(chis / 1e-5 - 1.0) < 1e-9):
+                near_ct += 1
+            else:
+                bad.append(((j, i), err))
+    print(f"[case] {len(pts)} samples, {near_ct} within rounding of C_T", flush=True)
+    assert not bad, bad[:5]
+
+
+def test_step_conserves_and_uses_the_oracle_time_step(problem):
+    pr = problem
+    print("[case] full-size step", flush=True)
+    sv = solver_for(pr)
+    U = torch.from_numpy(pr.U0).cuda()
+    tot0 = U.sum(dim=(1, 2)).cpu().numpy()
+    sv.run(U, 1, graph=True)
+    dt = sv.last_dt()
+    sv.poll()
+    tot1 = U.sum(dim=(1, 2)).cpu().numpy()
+    scale = torch.from_numpy(np.abs(pr.U0).sum(axis=(1, 2))).numpy()
+    assert np.all(np.abs(tot1 - tot0) <= 1e-13 * scale), (tot1 - tot0) / scale
+    _, den = O.wave_speeds(oracle_cfg(pr), pr.U0)
+    assert abs(dt - pr.cfl / den) <= 1e-14 * dt, (dt, pr.cfl / den)
+    Un = U.cpu().numpy()
+    rho = Un[0]
+    p = 0.4 * (Un[3] - 0.5 * (Un[1] ** 2 + Un[2] ** 2) / rho)
+    assert rho.min() > 0 and p.min() > 0

@@ -391,3 +391,23 @@ def test_sod_shock_tube_positive_and_non_oscillatory(orc):
     assert rho.min() > 0.125 - 2e-3 and rho.max() < 1.0 + 2e-3
     tv = np.abs(np.diff(rho)).sum()
     assert tv < 0.875 * 1.02, tv
+
+
+def test_window_evaluation_matches_the_full_domain(orc):
+    """The sampled full-size parity check evaluates one cell on a 17 x 17 window (outflow padding)
+    with the domain's Lax-Friedrichs constants: the cell depends only on cells within five along
+    its row and column, so the window reproduces the full periodic operator."""
+    pr = W.euler2d(4, n=256)
+    cfg = orc.Config(orc.EULER2D, 256, 256, 0.0, 1.0, 0.0, 1.0)
+    full = orc.rhs(cfg, pr.U0)
+    alpha, _ = orc.wave_speeds(cfg, pr.U0)
+    hw, w = 8, 17
+    wcfg = orc.Config(orc.EULER2D, w, w, 0.0, w * pr.dx, 0.0, w * pr.dy, orc.OUTFLOW, orc.OUTFLOW)
+    rng = np.random.default_rng(5)
+    pts = [tuple(p) for p in rng.integers(0, 256, size=(150, 2))] + [(0, 0), (255, 255), (127, 128), (128, 0)]
+    for (j, i) in pts:
+        rows = np.arange(j - hw, j + hw + 1) % 256
+        cols = np.arange(i - hw, i + hw + 1) % 256
+        Uw = np.ascontiguousarray(pr.U0[:, rows][:, :, cols])
+        o = orc.rhs(wcfg, Uw, alpha=alpha)[:, hw, hw]
+        assert np.array_equal(o, full[:, j, i]), (j, i, o - full[:, j, i])
