@@ -133,7 +133,7 @@ __global__ void __launch_bounds__(BLOCK, SYS == EULER1D ? 3 : (DIR == 0 ? TENO_M
 {
     constexpr int MODE = DIR == 0 ? MODE_STAGE : MODE_RHS;
     __shared__ T rec[NSEG * seg_stride<SYS>()];
-    __shared__ T ext[ext_size<T, SYS, DIR, NSEG, MODE>()];
+    __shared__ __align__(16) T ext[ext_size<T, SYS, DIR, NSEG, MODE>()];
     __shared__ T coef[NCOEF_ROWS * 8];
     __shared__ double red[BLOCK / WAVE * 9];
     const Item item = b.items[b.begin + xcd_tile(blockIdx.x, gridDim.x)];

@@ -85,6 +85,48 @@ __device__ __forceinline__ int bc_index(int i, int n, int bc)
     return i < 0 ? 0 : (i >= n ? n - 1 : i);
 }
 
+// Copy 64 consecutive elements of a row, starting at cell c >= 0 (cells past the row end read as 0),
+// straight from global memory into LDS at dst with the direct-to-LDS buffer load: no registers are
+// involved and the wave goes on at once; the copy completes under vmcnt. Each lane moves one dword
+// (so the copy is exact for any 4-byte alignment of dst and of the row), 256 bytes per instruction.
+// The buffer descriptor spans exactly the row, so offsets past its end return zeros instead of
+// touching other memory.
+template <typename T>
+__device__ __forceinline__ void lds_dma_row(const T *row, int nx, int c, T *dst, int lane)
+{
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc((void *)row, (short)0, nx * (int)sizeof(T), 0x00020000);
+    constexpr int CHUNK = WAVE * 4;                        // bytes per instruction
+#pragma unroll
+    for (int b = 0; b < WAVE * (int)sizeof(T); b += CHUNK)
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void *)((char *)dst + b), 4,
+                                                 c * (int)sizeof(T) + b + 4 * lane, 0, 0, 0);
+}
+
+// Workgroup barrier for LDS only: the wave's LDS operations complete (lgkmcnt 0), then s_barrier.
+// Unlike __syncthreads() it does not wait for outstanding vector-memory operations, so background
+// copies into a wave's own LDS area stay in flight. The empty asm statements keep the compiler from
+// moving memory accesses across it.
+__device__ __forceinline__ void lds_barrier()
+{
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(0xC07F);
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
+// A wave-uniform double moved into scalar registers.
+__device__ __forceinline__ double uniform_f64(double x)
+{
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readfirstlane((int)b), hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Wait for every outstanding vector-memory operation of the wave (vmcnt 0), including the
+// direct-to-LDS copies; lgkmcnt and expcnt are left alone.
+__device__ __forceinline__ void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
 // bc_index for -n <= i < 2n (one wrap at most, no division).
 __device__ __forceinline__ int bc_index_near(int i, int n, int bc)
 {
@@ -125,6 +167,19 @@ __device__ constexpr Rat COEF[NCOEF_ROWS][7] = {
 // TENO5 code (delta0<<2 | delta1<<1 | delta2) -> row of the table above. Code 0 cannot occur
 // (at least one chi_k >= 1/3 > C_T); it maps to the full stencil and is reported as an error.
 __device__ constexpr int TENO5_ROW[8] = {13, 16, 17, 14, 18, 19, 15, 13};
+
+// TENO5_ROW for a per-lane code without a memory lookup: the table packed into one 64-bit word.
+constexpr unsigned long long pack_teno5_rows()
+{
+    unsigned long long w = 0;
+    for (int k = 0; k < 8; ++k) w |= (unsigned long long)TENO5_ROW[k] << (8 * k);
+    return w;
+}
+__device__ __forceinline__ int teno5_row(int code)
+{
+    constexpr unsigned long long W = pack_teno5_rows();
+    return (int)((W >> (8 * (code & 7))) & 0xffull);
+}
 
 // Row R of the coefficient table applied to seven upwind-ordered values, with the constants folded
 // at compile time (each the correctly rounded quotient in T) and the zero taps dropped; the sum
@@ -590,6 +645,13 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
         }
     };
 
+    // Lax-Friedrichs constants of this direction and the stage's dt, read before any background copy
+    // is issued (vector-memory completions are waited for in order) and kept in scalar registers
+    double alv[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) alv[v] = v < NV ? uniform_f64(a.alpha[4 * DIR + v]) : 0.0;
+    const double dtv = MODE == MODE_STAGE ? uniform_f64(*a.dt) : 0.0;
+
     // ---- stage cells into LDS ----
     // x-sweeps: each wave stages its own segments (runs of SEG_LOAD cells of a row: coalesced, and
     // the index arithmetic is wave-uniform). y-sweeps: the block stages its NSEG adjacent columns
@@ -640,17 +702,17 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
                 stage_cell(s, q, lbase + g);
             }
             if constexpr (HAS_EXT) {
-                const bool want0 = MODE == MODE_STAGE, want1 = a.addend != nullptr;
-                const int c = c0 - 1 + lane;
-                if ((want0 || want1) && lane >= 1 && lane <= SEG_CELLS && c < a.len) {
-                    const size_t off = lbase + c;
-                    T *e = ext + (size_t)s * 2 * NV * WAVE + lane;
+                // the owned cells' U^n and y-part (lanes 1..61 read cells c0 .. c0+60): copied into
+                // LDS in the background (issued after the record loads, which are waited for in
+                // order); waited for just before the epilogue
+                // (slot element kk holds cell c0-1+kk; the copy fills elements 1..64, the last one
+                // landing on the next slot's unused element 0, or on the array's padding)
+                T *e = ext + (size_t)s * 2 * NV * WAVE + 1;
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) {
-                        const size_t go = (size_t)gvar<SYS, DIR>(v) * ncell + off;
-                        if (want0) e[v * WAVE] = a.U0[go];
-                        if (want1) e[(NV + v) * WAVE] = a.addend[go];
-                    }
+                for (int v = 0; v < NV; ++v) {
+                    const size_t fo = (size_t)gvar<SYS, DIR>(v) * ncell + lbase;
+                    if (MODE == MODE_STAGE) lds_dma_row(a.U0 + fo, a.nx, c0, e + v * WAVE, lane);
+                    if (a.addend) lds_dma_row(a.addend + fo, a.nx, c0, e + (NV + v) * WAVE, lane);
                 }
             }
         }
@@ -667,10 +729,8 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
             stage_cell(s, q, (size_t)g * a.nx + line);
         }
     }
-    __syncthreads();
+    lds_barrier();
 
-    const double *alpha = a.alpha + 4 * DIR;
-    double dtv = MODE == MODE_STAGE ? *a.dt : 0.0;
     // y-sweeps producing dU/dt leave their results in the segment's own LDS record and store the
     // tile row by row at the end (a lane's cells run down a column: direct stores would be strided)
     constexpr bool STAGE_OUT = DIR == 1 && MODE == MODE_RHS;
@@ -721,7 +781,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
 #pragma unroll 1
         for (int sf = 0; sf < NV; ++sf) {
             asm volatile("" ::: "memory");      // keep the stencil reads inside the field loop
-            const T al = (T)alpha[sf];
+            const T al = (T)(sf == 0 ? alv[0] : sf == 1 ? alv[1] : sf == 2 ? alv[2] : alv[3]);
             T Ls[NV], Rs[NV];
             char_basis<T, NV>(roe, sf, Ls, Rs);
             // the 1/2 of the splitting folded into L (exact scaling)
@@ -765,7 +825,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
             if constexpr (FROZEN) {
                 mp = (int)((mword_in >> (8 * sf)) & 15u);
                 mm = (int)((mword_in >> (8 * sf + 4)) & 15u);
-                if (a.scheme == 1) { mp = TENO5_ROW[mp & 7]; mm = TENO5_ROW[mm & 7]; }
+                if (a.scheme == 1) { mp = teno5_row(mp); mm = teno5_row(mm); }
             } else {
                 Smooth<T> sp = smooth5(vp[1], vp[2], vp[3], vp[4], vp[5]);
                 Smooth<T> sm = smooth5(vm[6], vm[5], vm[4], vm[3], vm[2]);
@@ -803,8 +863,8 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
                         int cm = (int)(((dm & 1u) << 2) | (dm & 2u) | ((dm >> 2) & 1u));
                         if (face_ok && (cp == 0 || cm == 0)) bad |= ERR_SELECTION;
                         mword |= (uint32_t)(cp | (cm << 4)) << (8 * sf);
-                        mp = TENO5_ROW[cp];
-                        mm = TENO5_ROW[cm];
+                        mp = teno5_row(cp);
+                        mm = teno5_row(cm);
                     }
                 }
             }
@@ -857,6 +917,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
         }
         if (a.masks_out && face_ok) a.masks_out[fidx] = mword;
         if constexpr (MODE != MODE_FACES) {
+            if constexpr (HAS_EXT) wait_vmem();  // the background copies of the epilogue operands
             T Fr[NV];
 #pragma unroll
             for (int v = 0; v < NV; ++v) Fr[v] = shfl_dn1(Fh[v]);
@@ -973,10 +1034,11 @@ __device__ __forceinline__ int xcd_tile(int b, int n)
     return x * q + min(x, r) + b / NXCD;
 }
 
-// LDS of the epilogue operands (x-sweeps that add a y-part or apply an RK stage).
+// LDS of the epilogue operands (x-sweeps that add a y-part or apply an RK stage): one 64-element
+// slot per segment and field, plus one element of padding for the last slot's copy overrun.
 template <typename T, int SYS, int DIR, int NSEG, int MODE> constexpr int ext_size()
 {
-    return (DIR == 0 && MODE != MODE_FACES) ? NSEG * 2 * Sys<SYS>::NV * WAVE : 1;
+    return (DIR == 0 && MODE != MODE_FACES) ? NSEG * 2 * Sys<SYS>::NV * WAVE + 2 : 1;
 }
 
 // One tile per block (measured faster on MI355X than persistent blocks looping over tiles: freshly
@@ -987,7 +1049,7 @@ __global__ void __launch_bounds__(BLOCK, SYS == EULER1D ? 3 : (DIR == 0 ? TENO_M
 {
     constexpr int NSEG = DIR == 0 ? NSEG_X : NSEG_Y;
     __shared__ T rec[NSEG * seg_stride<SYS>()];
-    __shared__ T ext[ext_size<T, SYS, DIR, NSEG, MODE>()];
+    __shared__ __align__(16) T ext[ext_size<T, SYS, DIR, NSEG, MODE>()];
     __shared__ T coef[NCOEF_ROWS * 8];
     __shared__ double red[BLOCK / WAVE * 9];
     fill_coef(coef);
