@@ -144,10 +144,12 @@ __global__ void __launch_bounds__(BLOCK, SYS == EULER1D ? 3 : (DIR == 0 ? TENO_M
     sweep_tile<T, SYS, DIR, false, NSEG, MODE>(a, item.tile, rec, ext, coef, red);        // staging barrier
     if (MODE == MODE_STAGE) {
         __syncthreads();
-        if (threadIdx.x < 9) {
+        int t = threadIdx.x;
+        asm volatile("" : "+v"(t));           // recomputed here, not kept live through the tile
+        if (t < 9) {
             double m = 0.0;
-            for (int q = 0; q < BLOCK / WAVE; ++q) m = fmax(m, red[q * 9 + threadIdx.x]);
-            atomicMax(&b.ictrl[item.inst].part[b.ring_next][blockIdx.x % NCOPY_B][threadIdx.x],
+            for (int q = 0; q < BLOCK / WAVE; ++q) m = fmax(m, red[q * 9 + t]);
+            atomicMax(&b.ictrl[item.inst].part[b.ring_next][blockIdx.x % NCOPY_B][t],
                       (unsigned long long)__double_as_longlong(m));
         }
     }

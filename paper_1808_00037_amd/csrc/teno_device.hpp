@@ -1058,11 +1058,13 @@ __global__ void __launch_bounds__(BLOCK, SYS == EULER1D ? 3 : (DIR == 0 ? TENO_M
                                                 red);                                     // staging barrier
     if (MODE == MODE_STAGE) {
         __syncthreads();
-        if (threadIdx.x < 9) {
+        int t = threadIdx.x;
+        asm volatile("" : "+v"(t));           // recomputed here, not kept live through the tile
+        if (t < 9) {
             double m = 0.0;
-            for (int q = 0; q < BLOCK / WAVE; ++q) m = fmax(m, red[q * 9 + threadIdx.x]);
+            for (int q = 0; q < BLOCK / WAVE; ++q) m = fmax(m, red[q * 9 + t]);
             unsigned long long *copy = a.part + (size_t)(blockIdx.x % NCOPY) * NWORD;
-            atomicMax(copy + threadIdx.x, (unsigned long long)__double_as_longlong(m));
+            atomicMax(copy + t, (unsigned long long)__double_as_longlong(m));
         }
     }
 }
