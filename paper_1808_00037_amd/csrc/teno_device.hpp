@@ -70,6 +70,15 @@ template <> struct Sys<EULER2D> {
     static constexpr int NV = 4, NREC = 9, E = 3, UN = 4, UT = 5, P = 6, S = 7, H = 8;
 };
 
+// Staged per-cell record of the forward sweeps: the conserved variables in local order, then u_n,
+// [u_t], p and 1/sqrt(rho) (sqrt(rho) = rho / sqrt(rho) and H sqrt(rho) = (E + p) / sqrt(rho) are
+// recovered in the Roe average, which keeps the record one value shorter than with H).
+template <int SYS> struct Rec;
+template <> struct Rec<ADV1D> { static constexpr int NREC = 1; };
+template <> struct Rec<BURGERS1D> { static constexpr int NREC = 1; };
+template <> struct Rec<EULER1D> { static constexpr int NREC = 6, E = 2, UN = 3, UT = -1, P = 4, RS = 5; };
+template <> struct Rec<EULER2D> { static constexpr int NREC = 8, E = 3, UN = 4, UT = 5, P = 6, RS = 7; };
+
 // Global variable index of local (normal/tangential) component v in direction DIR.
 template <int SYS, int DIR> __device__ __forceinline__ constexpr int gvar(int v)
 {
@@ -597,11 +606,11 @@ __device__ __forceinline__ void block_max_atomic(double w[9], unsigned long long
 #define TENO_MIN_WAVES_X 4
 #endif
 #ifndef TENO_MIN_WAVES_Y
-#define TENO_MIN_WAVES_Y 3
+#define TENO_MIN_WAVES_Y 4
 #endif
 
 // LDS record stride of one staged segment (odd: the y staging stores spread over the banks).
-template <int SYS> constexpr int seg_stride() { return Sys<SYS>::NREC * SEG_LOAD + 1; }
+template <int SYS> constexpr int seg_stride() { return Rec<SYS>::NREC * SEG_LOAD + 1; }
 
 // Fill the block's coefficient table (rows of Tables 2 and 1, correctly rounded in T).
 template <typename T> __device__ __forceinline__ void fill_coef(T *coef)
@@ -664,14 +673,14 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
         if constexpr (!EULER) {
             r[0] = a.U[off];
         } else {
-            using S = Sys<SYS>;
+            using S = Rec<SYS>;
             T rho = a.U[off];
             T mn = a.U[(size_t)gvar<SYS, DIR>(1) * ncell + off];
             T mt = NV == 4 ? a.U[(size_t)gvar<SYS, DIR>(2) * ncell + off] : T(0);
             T E = a.U[(size_t)(NV - 1) * ncell + off];
-            T sq, ir;
-            sqrt_rsqrt(rho, sq, ir);
-            ir = ir * ir;
+            T sq, rs;
+            sqrt_rsqrt(rho, sq, rs);
+            T ir = rs * rs;
             if (!(rho > T(0))) ir = T(1) / rho;
             T un = mn * ir, ut = mt * ir;
             T p = a.gm1 * (E - T(0.5) * rho * (un * un + ut * ut));
@@ -683,8 +692,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
             r[SEG_LOAD * S::UN] = un;
             if constexpr (NV == 4) r[SEG_LOAD * S::UT] = ut;
             r[SEG_LOAD * S::P] = p;
-            r[SEG_LOAD * S::S] = sq;
-            r[SEG_LOAD * S::H] = (E + p) * ir;
+            r[SEG_LOAD * S::RS] = rs;
         }
     };
     // epilogue operands of the owned cells (lanes 1..61), staged with the tile so that their
@@ -746,10 +754,12 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
         const int f = c0 - 1 + k;               // this lane's face
         bool face_ok = k >= 1 && k <= 62 && f <= a.len;
         bool cell_ok = k >= 1 && k <= 61 && f < a.len;
-        size_t fidx = 0;                        // face index in this direction's face arrays
-        if (face_ok) fidx = DIR == 0 ? (size_t)line * (a.len + 1) + f : (size_t)f * a.nx + line;
+        // face index in this direction's face arrays
+        auto face_index = [&](int ff) {
+            return DIR == 0 ? (size_t)line * (a.len + 1) + ff : (size_t)ff * a.nx + line;
+        };
         uint32_t mword_in = 0;
-        if constexpr (FROZEN) mword_in = face_ok ? a.masks_in[fidx] : 0u;
+        if constexpr (FROZEN) mword_in = face_ok ? a.masks_in[face_index(f)] : 0u;
 
         T Fh[NV];
 #pragma unroll
@@ -759,15 +769,18 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
         // Roe-averaged state of the face (cells i = q k+3 and i+1 = q k+4, Remark 3)
         Roe<T> roe;
         if constexpr (EULER) {
-            using S = Sys<SYS>;
+            using S = Rec<SYS>;
             const T gm1 = a.gm1;
-            T sL = R0[SEG_LOAD * S::S + k + 3], sR = R0[SEG_LOAD * S::S + k + 4];
+            const T rsL = R0[SEG_LOAD * S::RS + k + 3], rsR = R0[SEG_LOAD * S::RS + k + 4];
+            const T sL = R0[k + 3] * rsL, sR = R0[k + 4] * rsR;          // sqrt(rho)
             T isum = recip(sL + sR);
             roe.un = (sL * R0[SEG_LOAD * S::UN + k + 3] + sR * R0[SEG_LOAD * S::UN + k + 4]) * isum;
             roe.ut = T(0);
             if constexpr (NV == 4)
                 roe.ut = (sL * R0[SEG_LOAD * S::UT + k + 3] + sR * R0[SEG_LOAD * S::UT + k + 4]) * isum;
-            roe.H = (sL * R0[SEG_LOAD * S::H + k + 3] + sR * R0[SEG_LOAD * S::H + k + 4]) * isum;
+            // sqrt(rho) H = (E + p) / sqrt(rho)
+            roe.H = ((R0[SEG_LOAD * S::E + k + 3] + R0[SEG_LOAD * S::P + k + 3]) * rsL +
+                     (R0[SEG_LOAD * S::E + k + 4] + R0[SEG_LOAD * S::P + k + 4]) * rsR) * isum;
             roe.q2 = roe.un * roe.un + roe.ut * roe.ut;
             T c2 = gm1 * (roe.H - T(0.5) * roe.q2);
             if (face_ok && !(c2 > T(0))) bad |= isfinite(c2) ? ERR_NONPHYSICAL : ERR_NONFINITE;
@@ -794,7 +807,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
                 for (int j = 0; j < 8; ++j) {
                     const int q = k + j;
                     T lu = R0[SEG_LOAD * 2 + q] * Ls[2] + Ls[0] * R0[q];
-                    T lf = R0[SEG_LOAD * Sys<EULER2D>::UN + q] * lu;
+                    T lf = R0[SEG_LOAD * Rec<EULER2D>::UN + q] * lu;
                     vp[j] = lf + al * lu;
                     vm[j] = lf - al * lu;
                 }
@@ -808,7 +821,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
                         lu = T(0.5) * u;
                         lf = SYS == ADV1D ? a.adv * lu : lu * u * T(0.5);
                     } else {
-                        using S = Sys<SYS>;
+                        using S = Rec<SYS>;
                         T un = R0[SEG_LOAD * S::UN + q], p = R0[SEG_LOAD * S::P + q];
                         lu = Ls[0] * R0[q];
 #pragma unroll
@@ -896,26 +909,27 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
         // ---- epilogue ----
         // lane-dependent predicates recomputed from an opaque copy of the lane id (keeping them
         // live across the field loop costs registers the loop needs)
+        int fe;                                 // this lane's face again
         {
             int kk = lane;
             asm volatile("" : "+v"(kk) : : "memory");   // also orders the record reads before the epilogue
-            const int ff = c0 - 1 + kk;
-            face_ok = kk >= 1 && kk <= 62 && ff <= a.len;
-            cell_ok = kk >= 1 && kk <= 61 && ff < a.len;
+            fe = c0 - 1 + kk;
+            face_ok = kk >= 1 && kk <= 62 && fe <= a.len;
+            cell_ok = kk >= 1 && kk <= 61 && fe < a.len;
         }
         if constexpr (MODE == MODE_FACES) {
             if (face_ok) {
 #pragma unroll
                 for (int v = 0; v < NV; ++v) {
                     int gv = gvar<SYS, DIR>(v);
-                    size_t o = DIR == 0 ? ((size_t)gv * a.ny + line) * (a.len + 1) + f
-                                        : ((size_t)gv * (a.len + 1) + f) * a.nx + line;
+                    size_t o = DIR == 0 ? ((size_t)gv * a.ny + line) * (a.len + 1) + fe
+                                        : ((size_t)gv * (a.len + 1) + fe) * a.nx + line;
                     a.Fout[o] = Fh[v];
                 }
-                if (a.flags_out) a.flags_out[fidx] = fword;
+                if (a.flags_out) a.flags_out[face_index(fe)] = fword;
             }
         }
-        if (a.masks_out && face_ok) a.masks_out[fidx] = mword;
+        if (a.masks_out && face_ok) a.masks_out[face_index(fe)] = mword;
         if constexpr (MODE != MODE_FACES) {
             if constexpr (HAS_EXT) wait_vmem();  // the background copies of the epilogue operands
             T Fr[NV];
@@ -924,7 +938,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
             // primitive speeds of the produced cell (stage mode); lanes without a cell contribute 0
             double sx = 0.0, sy = 0.0, sc = 0.0;
             if (cell_ok) {
-                size_t off = DIR == 0 ? (size_t)line * a.nx + f : (size_t)f * a.nx + line;
+                size_t off = DIR == 0 ? (size_t)line * a.nx + fe : (size_t)fe * a.nx + line;
                 const T *e = ext + (size_t)s * 2 * NV * WAVE + k;
                 T unew[NV];
 #pragma unroll
