@@ -140,7 +140,11 @@ __global__ void __launch_bounds__(BLOCK) vjp_kernel(VjpArgs a)
     }
     __syncthreads();
 
-    const double *alpha = a.alpha + 4 * DIR;
+    // Lax-Friedrichs constants in scalar registers (a vector load inside the stencil loop would wait
+    // on every outstanding memory operation of the wave)
+    double alpha[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) alpha[v] = v < NV ? uniform_f64(a.alpha[4 * DIR + v]) : 0.0;
     const double gm1 = a.gamma - 1.0;
 
     for (int s = wid; s < ADJ_NSEG; s += BLOCK / WAVE) {
