@@ -719,7 +719,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
 #pragma unroll
                 for (int v = 0; v < NV; ++v) {
                     const size_t fo = (size_t)gvar<SYS, DIR>(v) * ncell + lbase;
-                    if (MODE == MODE_STAGE) lds_dma_row(a.U0 + fo, a.nx, c0, e + v * WAVE, lane);
+                    if (MODE == MODE_STAGE && a.U0 != a.U) lds_dma_row(a.U0 + fo, a.nx, c0, e + v * WAVE, lane);
                     if (a.addend) lds_dma_row(a.addend + fo, a.nx, c0, e + (NV + v) * WAVE, lane);
                 }
             }
@@ -953,7 +953,8 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
                     } else {
                         // SSP-RK3 stage, Shu-Osher form
                         T uk = R0[SEG_LOAD * v + k + 4];   // staged record: conserved variable v first
-                        T u0 = HAS_EXT ? e[v * WAVE] : a.U0[go];
+                        // U^n: the staged stage input itself at the first stage, else its copy
+                        T u0 = HAS_EXT ? (a.U0 == a.U ? uk : e[v * WAVE]) : a.U0[go];
                         T dt = (T)dtv;
                         T un;
                         if (a.stage == 0) un = u0 + dt * d;
