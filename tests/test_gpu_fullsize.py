@@ -98,3 +98,39 @@ def test_step_conserves_and_uses_the_oracle_time_step(problem):
     rho = Un[0]
     p = 0.4 * (Un[3] - 0.5 * (Un[1] ** 2 + Un[2] ** 2) / rho)
     assert rho.min() > 0 and p.min() > 0
+
+
+def test_arrays_beyond_4_gib():
+    """16384 x 8192 cells (4.3 GB per state, 2^33 bytes and more): no index of the sweeps, the
+    stage update or the boundary handling may wrap at 32 bits. Sampled cells against oracle windows
+    (the oracle's constants from the whole state) and the conservation of one step."""
+    pr = W.euler2d(2, n=16384, ny=8192)
+    print("[case] 16384 x 8192 rhs", flush=True)
+    sv = solver_for(pr)
+    U = torch.from_numpy(pr.U0).cuda()
+    g = sv.rhs(U)
+    rng = np.random.default_rng(13)
+    rows = np.concatenate([rng.integers(0, pr.ny, size=150), [0, pr.ny - 1, pr.ny // 2, pr.ny // 2 - 1]])
+    cols = np.concatenate([rng.integers(0, pr.nx, size=150), [0, pr.nx - 1, pr.nx // 2, pr.nx // 2 - 1]])
+    pts = sorted(set(zip(rows.tolist(), cols.tolist())) | {(pr.ny - 1, pr.nx - 1), (pr.ny - 1, 0)})
+    gs = {p: g[:, p[0], p[1]].cpu().numpy() for p in pts}
+    del g
+    alpha, den = O.wave_speeds(oracle_cfg(pr), pr.U0)
+    w = 2 * HW + 1
+    wcfg = O.Config(O.EULER2D, w, w, 0.0, w * pr.dx, 0.0, w * pr.dy, O.OUTFLOW, O.OUTFLOW)
+    for (j, i) in pts:
+        rr = np.arange(j - HW, j + HW + 1) % pr.ny
+        cc = np.arange(i - HW, i + HW + 1) % pr.nx
+        Uw = np.ascontiguousarray(pr.U0[:, rr][:, :, cc])
+        o = O.rhs(wcfg, Uw, alpha=alpha)[:, HW, HW]
+        err = np.abs(gs[(j, i)] - o).max() * pr.dx / max(np.abs(Uw).max(), 1.0)
+        assert err <= 4e-12, ((j, i), err)
+    print("[case] 16384 x 8192 step", flush=True)
+    tot0 = U.sum(dim=(1, 2)).cpu().numpy()
+    sv.run(U, 1, graph=False)
+    dt = sv.last_dt()
+    sv.poll()
+    tot1 = U.sum(dim=(1, 2)).cpu().numpy()
+    scale = np.abs(pr.U0).sum(axis=(1, 2))
+    assert np.all(np.abs(tot1 - tot0) <= 1e-13 * scale)
+    assert abs(dt - pr.cfl / den) <= 1e-14 * dt
