@@ -796,7 +796,15 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
             asm volatile("" ::: "memory");      // keep the stencil reads inside the field loop
             const T al = (T)(sf == 0 ? alv[0] : sf == 1 ? alv[1] : sf == 2 ? alv[2] : alv[3]);
             T Ls[NV], Rs[NV];
-            char_basis<T, NV>(roe, sf, Ls, Rs);
+            {
+                // computed here for this field only: an opaque copy of the face state keeps the
+                // compiler from hoisting all fields' rows out of the loop (registers held across it
+                // plus copies into place every iteration)
+                Roe<T> rr = roe;
+                asm volatile("" : "+v"(rr.un), "+v"(rr.ut), "+v"(rr.cs), "+v"(rr.ic), "+v"(rr.H), "+v"(rr.q2),
+                                  "+v"(rr.b1), "+v"(rr.b2));
+                char_basis<T, NV>(rr, sf, Ls, Rs);
+            }
             // the 1/2 of the splitting folded into L (exact scaling)
 #pragma unroll
             for (int v = 0; v < NV; ++v) Ls[v] *= T(0.5);
