@@ -139,18 +139,21 @@ __global__ void __launch_bounds__(BLOCK, SYS == EULER1D ? 3 : (DIR == 0 ? TENO_M
     const Item item = b.items[b.begin + xcd_tile(blockIdx.x, gridDim.x)];
     const BatchInst I = b.inst[item.inst];
     const SweepArgs<T> a = item_args<T, SYS, DIR>(b, I, item.inst);
+    const bool wave0 = __builtin_amdgcn_readfirstlane(threadIdx.x) < WAVE;   // wave-uniform
     fill_coef(coef);
     if (MODE == MODE_STAGE && threadIdx.x < BLOCK / WAVE * 9) red[threadIdx.x] = 0.0;   // ordered by the
     sweep_tile<T, SYS, DIR, false, NSEG, MODE>(a, item.tile, rec, ext, coef, red);        // staging barrier
     if (MODE == MODE_STAGE) {
         __syncthreads();
-        int t = threadIdx.x;
-        asm volatile("" : "+v"(t));           // recomputed here, not kept live through the tile
-        if (t < 9) {
-            double m = 0.0;
-            for (int q = 0; q < BLOCK / WAVE; ++q) m = fmax(m, red[q * 9 + t]);
-            atomicMax(&b.ictrl[item.inst].part[b.ring_next][blockIdx.x % NCOPY_B][t],
-                      (unsigned long long)__double_as_longlong(m));
+        // lanes 0..8 of wave 0 (no thread index kept live through the tile)
+        if (wave0) {
+            const int t = lane_id_now();
+            if (t < 9) {
+                double m = 0.0;
+                for (int q = 0; q < BLOCK / WAVE; ++q) m = fmax(m, red[q * 9 + t]);
+                atomicMax(&b.ictrl[item.inst].part[b.ring_next][blockIdx.x % NCOPY_B][t],
+                          (unsigned long long)__double_as_longlong(m));
+            }
         }
     }
 }

@@ -124,6 +124,17 @@ __device__ __forceinline__ void lds_barrier()
     asm volatile("" ::: "memory");
 }
 
+// Lane number within the wave, recomputed where it is used (two ALU instructions) rather than kept
+// in a register from the start of the kernel as threadIdx.x would be. Volatile, so the compiler
+// neither merges nor hoists it.
+__device__ __forceinline__ int lane_id_now()
+{
+    int lo, id;
+    asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0" : "=v"(lo));
+    asm volatile("v_mbcnt_hi_u32_b32 %0, -1, %1" : "=v"(id) : "v"(lo));
+    return id;
+}
+
 // A wave-uniform double moved into scalar registers.
 __device__ __forceinline__ double uniform_f64(double x)
 {
@@ -750,7 +761,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
         seg_of(s, line, c0);
         if (line < 0) continue;                 // wave-uniform
         const T *R0 = rec + s * SEG_STRIDE;
-        const int k = lane;
+        const int k = lane_id_now();
         const int f = c0 - 1 + k;               // this lane's face
         bool face_ok = k >= 1 && k <= 62 && f <= a.len;
         bool cell_ok = k >= 1 && k <= 61 && f < a.len;
@@ -894,10 +905,6 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
                 // Table 2 row 0 (the seventh-order linear scheme) as compile-time constants
                 hp = recon_const<T, 0>(vp[0], vp[1], vp[2], vp[3], vp[4], vp[5], vp[6]);
                 hm = recon_const<T, 0>(vm[7], vm[6], vm[5], vm[4], vm[3], vm[2], vm[1]);
-            } else if (a.scheme == 1 && __all(mp == TENO5_ROW[7] && mm == TENO5_ROW[7])) {
-                // TENO5 with every flag kept: its fifth-order linear scheme (Table 1, 111)
-                hp = recon_const<T, TENO5_ROW[7]>(vp[0], vp[1], vp[2], vp[3], vp[4], vp[5], vp[6]);
-                hm = recon_const<T, TENO5_ROW[7]>(vm[7], vm[6], vm[5], vm[4], vm[3], vm[2], vm[1]);
             } else {
                 const T *cp_ = coef + mp * 8;
                 const T *cm_ = coef + mm * 8;
@@ -919,8 +926,8 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
         // live across the field loop costs registers the loop needs)
         int fe;                                 // this lane's face again
         {
-            int kk = lane;
-            asm volatile("" : "+v"(kk) : : "memory");   // also orders the record reads before the epilogue
+            int kk = lane_id_now();
+            asm volatile("" ::: "memory");      // orders the record reads before the epilogue
             fe = c0 - 1 + kk;
             face_ok = kk >= 1 && kk <= 62 && fe <= a.len;
             cell_ok = kk >= 1 && kk <= 61 && fe < a.len;
@@ -1003,7 +1010,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
                 for (int q = 0; q < 9; ++q) {
                     if (!USE[q]) continue;
                     const double m = __longlong_as_double((long long)(((unsigned long long)mh[q] << 32) | ml[q]));
-                    if (lane == 0) {
+                    if (k == 0) {
                         red[wid * 9 + q] = fmax(red[wid * 9 + q], m);
                         if (NV == 4 && (q == 1 || q == 5)) red[wid * 9 + q + 1] = fmax(red[wid * 9 + q + 1], m);
                     }
@@ -1075,19 +1082,23 @@ __global__ void __launch_bounds__(BLOCK, SYS == EULER1D ? 3 : (DIR == 0 ? TENO_M
     __shared__ __align__(16) T ext[ext_size<T, SYS, DIR, NSEG, MODE>()];
     __shared__ T coef[NCOEF_ROWS * 8];
     __shared__ double red[BLOCK / WAVE * 9];
+    const bool wave0 = __builtin_amdgcn_readfirstlane(threadIdx.x) < WAVE;   // wave-uniform
     fill_coef(coef);
     if (MODE == MODE_STAGE && threadIdx.x < BLOCK / WAVE * 9) red[threadIdx.x] = 0.0;   // ordered by the
     sweep_tile<T, SYS, DIR, FROZEN, NSEG, MODE>(a, xcd_tile(blockIdx.x, gridDim.x), rec, ext, coef,
                                                 red);                                     // staging barrier
     if (MODE == MODE_STAGE) {
         __syncthreads();
-        int t = threadIdx.x;
-        asm volatile("" : "+v"(t));           // recomputed here, not kept live through the tile
-        if (t < 9) {
-            double m = 0.0;
-            for (int q = 0; q < BLOCK / WAVE; ++q) m = fmax(m, red[q * 9 + t]);
-            unsigned long long *copy = a.part + (size_t)(blockIdx.x % NCOPY) * NWORD;
-            atomicMax(copy + t, (unsigned long long)__double_as_longlong(m));
+        // lanes 0..8 of wave 0; the wave index is wave-uniform (scalar) and the lane number is
+        // recomputed, so no thread index stays live through the tile
+        if (wave0) {
+            const int t = lane_id_now();
+            if (t < 9) {
+                double m = 0.0;
+                for (int q = 0; q < BLOCK / WAVE; ++q) m = fmax(m, red[q * 9 + t]);
+                unsigned long long *copy = a.part + (size_t)(blockIdx.x % NCOPY) * NWORD;
+                atomicMax(copy + t, (unsigned long long)__double_as_longlong(m));
+            }
         }
     }
 }
