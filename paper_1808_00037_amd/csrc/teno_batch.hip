@@ -251,8 +251,9 @@ struct teno_batch {
     // tuned launch shape
     bool tuned = false;
     int vx = 0, vy = 1;
-    // captured run
-    hipStream_t cap_stream = nullptr;
+    // captured run (a second stream for the parallel branch of the 1D instances)
+    hipStream_t cap_stream = nullptr, cap_stream2 = nullptr;
+    hipEvent_t ev_fork[3] = {nullptr, nullptr, nullptr}, ev_join[3] = {nullptr, nullptr, nullptr};
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     void *graph_U = nullptr;
@@ -311,9 +312,12 @@ Ranges instance_ranges(const teno_batch *b, int k, int vx, int vy)
     return r;
 }
 
-// Enqueue one SSP-RK3 step of the instances [first, first + count) whose items are r.
+// Enqueue one SSP-RK3 step of the instances [first, first + count) whose items are r. With a second
+// stream s2 (graph capture), the 1D instances' x-sweep runs on a parallel branch beside the 2D
+// sweeps (it depends on neither) and joins before the next stage.
 template <typename T>
-void enqueue_step(teno_batch *b, hipStream_t s, T *U, int first, int count, const Ranges &r, int vx, int vy)
+void enqueue_step(teno_batch *b, hipStream_t s, T *U, int first, int count, const Ranges &r, int vx, int vy,
+                  hipStream_t s2 = nullptr)
 {
     T *in[3] = {U, (T *)b->S1, (T *)b->S2};
     T *outp[3] = {(T *)b->S1, (T *)b->S2, U};
@@ -335,12 +339,26 @@ void enqueue_step(teno_batch *b, hipStream_t s, T *U, int first, int count, cons
         a.addend = (T *)b->dUy;
         a.out = outp[k];
         a.ring_next = (k + 1) % 3;
+        const bool fork = s2 != nullptr && r.x1b > r.x1a;
+        if (fork) {
+            (void)hipEventRecord(b->ev_fork[k], s);
+            (void)hipStreamWaitEvent(s2, b->ev_fork[k], 0);
+            BatchSweep<T> a1 = a;
+            a1.begin = r.x1a;
+            a1.end = r.x1b;
+            launch_batch_sweep<T, EULER1D, 0>(s2, vx, a1);
+            (void)hipEventRecord(b->ev_join[k], s2);
+        }
         a.begin = r.x2a;
         a.end = r.x2b;
         launch_batch_sweep<T, EULER2D, 0>(s, vx, a);
-        a.begin = r.x1a;
-        a.end = r.x1b;
-        launch_batch_sweep<T, EULER1D, 0>(s, vx, a);
+        if (fork) {
+            (void)hipStreamWaitEvent(s, b->ev_join[k], 0);
+        } else {
+            a.begin = r.x1a;
+            a.end = r.x1b;
+            launch_batch_sweep<T, EULER1D, 0>(s, vx, a);
+        }
     }
 }
 
@@ -404,10 +422,16 @@ teno_status run_t(teno_batch *b, T *U, int nsteps, int mode)
         b->exec = nullptr;
         b->graph = nullptr;
         if (!b->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+        if (!b->cap_stream2) HIP_TRY(hipStreamCreateWithFlags(&b->cap_stream2, hipStreamNonBlocking));
+        for (int k = 0; k < 3; ++k) {
+            if (!b->ev_fork[k]) HIP_TRY(hipEventCreateWithFlags(&b->ev_fork[k], hipEventDisableTiming));
+            if (!b->ev_join[k]) HIP_TRY(hipEventCreateWithFlags(&b->ev_join[k], hipEventDisableTiming));
+        }
         HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
         enqueue_init<T>(b, b->cap_stream, U, 0, b->n);
         const Ranges r = all_ranges(b, b->vx, b->vy);
-        for (int n = 0; n < nsteps; ++n) enqueue_step<T>(b, b->cap_stream, U, 0, b->n, r, b->vx, b->vy);
+        for (int n = 0; n < nsteps; ++n)
+            enqueue_step<T>(b, b->cap_stream, U, 0, b->n, r, b->vx, b->vy, b->cap_stream2);
         HIP_TRY(hipStreamEndCapture(b->cap_stream, &b->graph));
         HIP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
         b->graph_U = U;
@@ -546,6 +570,11 @@ teno_status teno_batch_destroy(teno_batch *b)
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+    if (b->cap_stream2) (void)hipStreamDestroy(b->cap_stream2);
+    for (int k = 0; k < 3; ++k) {
+        if (b->ev_fork[k]) (void)hipEventDestroy(b->ev_fork[k]);
+        if (b->ev_join[k]) (void)hipEventDestroy(b->ev_join[k]);
+    }
     for (int v = 0; v < 2; ++v) {
         (void)hipFree(b->items_x_d[v]);
         (void)hipFree(b->items_y_d[v]);
