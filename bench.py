@@ -221,6 +221,42 @@ def scheme_cost(n=4096, steps=10, seed=1):
     return res
 
 
+def fp32_run(n=4096, steps=10, n_err=256, steps_err=20, seed=1):
+    """Single precision: SSP-RK3 throughput on the same 4096^2 state, and the error of a 256^2 run of
+    steps_err steps against the FP64 oracle's trajectory (L1 and max norms, relative to the
+    oracle's state)."""
+    import numpy as np
+    import torch
+    from oracle import oracle as O
+    from paper_1808_00037_amd import teno as T
+    from paper_1808_00037_amd import workloads as W
+
+    pr = W.euler2d(seed, n=n)
+    sv = T.Solver.for_problem(pr, dtype=torch.float32)
+    U = torch.from_numpy(pr.U0.astype(np.float32)).cuda()
+    sv.run(U, 2, graph=True)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    sv.run(U, steps, graph=True)
+    e1.record()
+    torch.cuda.synchronize()
+    sv.poll()
+    ms = e0.elapsed_time(e1) / steps
+    del sv, U
+    pe = W.euler2d(seed, n=n_err)
+    cfg = O.Config(O.EULER2D, n_err, n_err, 0.0, 1.0, 0.0, 1.0)
+    Uo = O.run(cfg, pe.U0, steps_err, cfl=pe.cfl)
+    sv = T.Solver.for_problem(pe, dtype=torch.float32)
+    Ug = torch.from_numpy(pe.U0.astype(np.float32)).cuda()
+    sv.run(Ug, steps_err, graph=False)
+    sv.poll()
+    d = Ug.double().cpu().numpy() - Uo
+    return {"n": n, "ms_per_step": ms, "Gcell_updates_per_s": n * n * 3 / (ms / 1e3) / 1e9,
+            "error_run": f"{n_err}x{n_err}, {steps_err} steps vs the FP64 oracle",
+            "rel_L1": float(np.abs(d).sum() / np.abs(Uo).sum()), "rel_Linf": float(np.abs(d).max() / np.abs(Uo).max())}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -321,6 +357,10 @@ def main():
         log("batched vs one launch per instance (512 instances)")
         out["batched"] = batched_speedup()
         log(json.dumps(out["batched"]))
+        torch.cuda.empty_cache()
+        log("FP32 throughput and error against the FP64 oracle")
+        out["fp32"] = fp32_run(n=n)
+        log(json.dumps(out["fp32"]))
         torch.cuda.empty_cache()
         log("TENO7X vs TENO5 step cost")
         out["scheme_cost"] = scheme_cost(n=n)
