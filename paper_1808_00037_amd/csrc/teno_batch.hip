@@ -143,19 +143,7 @@ __global__ void __launch_bounds__(BLOCK, SYS == EULER1D ? 3 : (DIR == 0 ? TENO_M
     fill_coef(coef);
     if (MODE == MODE_STAGE && threadIdx.x < BLOCK / WAVE * 9) red[threadIdx.x] = 0.0;   // ordered by the
     sweep_tile<T, SYS, DIR, false, NSEG, MODE>(a, item.tile, rec, ext, coef, red);        // staging barrier
-    if (MODE == MODE_STAGE) {
-        __syncthreads();
-        // lanes 0..8 of wave 0 (no thread index kept live through the tile)
-        if (wave0) {
-            const int t = lane_id_now();
-            if (t < 9) {
-                double m = 0.0;
-                for (int q = 0; q < BLOCK / WAVE; ++q) m = fmax(m, red[q * 9 + t]);
-                atomicMax(&b.ictrl[item.inst].part[b.ring_next][blockIdx.x % NCOPY_B][t],
-                          (unsigned long long)__double_as_longlong(m));
-            }
-        }
-    }
+    if (MODE == MODE_STAGE) flush_block_maxima(red, &b.ictrl[item.inst].part[b.ring_next][blockIdx.x % NCOPY_B][0], wave0);
 }
 
 // Wave-speed maxima of every instance of a packed state (items: (instance, chunk of WS_CHUNK cells)).

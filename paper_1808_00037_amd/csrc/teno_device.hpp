@@ -9,12 +9,14 @@
 //     have both neighbour faces in the same wave and finish the reconstruction; lanes 1..61 own
 //     cells c0 .. c0+60 and apply the conservative difference. Consecutive segments start 61 cells
 //     apart, so every face and cell is finished by exactly the lanes that can finish it.
-//   * The block stages its segments' cells (conserved variables plus per-cell velocity, pressure,
-//     sqrt(rho) and enthalpy, computed once per cell) in LDS; every lane then reads its eight
-//     stencil cells from LDS. x-sweeps stage 4 consecutive segments of a row (coalesced);
+//   * Segment cells are staged in LDS (conserved variables plus velocity, pressure and
+//     1/sqrt(rho), computed once per cell); every lane then reads its eight stencil cells from LDS.
+//     In x-sweeps each wave stages its own segment (a coalesced run of a row, wave-uniform index
+//     arithmetic) and the stage operands of its cells arrive by background direct-to-LDS copies;
 //     y-sweeps stage 8 adjacent columns with the same rows so that a global load of one row reads
-//     8 consecutive doubles; LDS holds each column contiguously, so lanes running along y read
-//     consecutive LDS words.
+//     8 consecutive doubles, and write their results back through LDS row by row. LDS holds each
+//     segment contiguously, so lanes read consecutive LDS words.
+//   * Tiles are renumbered per XCD so that neighbouring tiles share an L2.
 //   * The neighbour flags of eq:vec come from lanes k-1 and k+1 through cross-lane shuffles; no
 //     flag array is stored (the paper's whole-domain flag pass lives in registers).
 //   * Characteristic fields are streamed one at a time: project eight points, cut-off flags on
@@ -1032,25 +1034,20 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
     if (bad) atomicOr(a.err, bad);
 }
 
-// Per-wave maxima slots of a block (MODE_STAGE): cleared before the first tile, flushed (one
-// atomic maximum per word into a spread copy) when the block is done with an instance.
-__device__ __forceinline__ void clear_maxima(double *red)
-{
-    if (threadIdx.x < BLOCK / WAVE * 9) red[threadIdx.x] = 0.0;
-    __syncthreads();
-}
-
-__device__ __forceinline__ void flush_maxima(double *red, unsigned long long *copy)
+// End of a MODE_STAGE block: the per-wave maxima slots reduced by lanes 0..8 of wave 0, one atomic
+// maximum per word into one spread copy. wave0 is wave-uniform and the lane number is recomputed, so
+// no thread index has to stay live through the tile.
+__device__ __forceinline__ void flush_block_maxima(const double *red, unsigned long long *copy, bool wave0)
 {
     __syncthreads();
-    if (threadIdx.x < 9) {
-        double m = 0.0;
-        for (int q = 0; q < BLOCK / WAVE; ++q) m = fmax(m, red[q * 9 + threadIdx.x]);
-        atomicMax(copy + threadIdx.x, (unsigned long long)__double_as_longlong(m));
+    if (wave0) {
+        const int t = lane_id_now();
+        if (t < 9) {
+            double m = 0.0;
+            for (int q = 0; q < BLOCK / WAVE; ++q) m = fmax(m, red[q * 9 + t]);
+            atomicMax(copy + t, (unsigned long long)__double_as_longlong(m));
+        }
     }
-    __syncthreads();
-    if (threadIdx.x < BLOCK / WAVE * 9) red[threadIdx.x] = 0.0;
-    __syncthreads();
 }
 
 // Workgroups of a launch are handed to the 8 XCDs round-robin (block b to XCD b mod 8), and each
@@ -1087,20 +1084,7 @@ __global__ void __launch_bounds__(BLOCK, SYS == EULER1D ? 3 : (DIR == 0 ? TENO_M
     if (MODE == MODE_STAGE && threadIdx.x < BLOCK / WAVE * 9) red[threadIdx.x] = 0.0;   // ordered by the
     sweep_tile<T, SYS, DIR, FROZEN, NSEG, MODE>(a, xcd_tile(blockIdx.x, gridDim.x), rec, ext, coef,
                                                 red);                                     // staging barrier
-    if (MODE == MODE_STAGE) {
-        __syncthreads();
-        // lanes 0..8 of wave 0; the wave index is wave-uniform (scalar) and the lane number is
-        // recomputed, so no thread index stays live through the tile
-        if (wave0) {
-            const int t = lane_id_now();
-            if (t < 9) {
-                double m = 0.0;
-                for (int q = 0; q < BLOCK / WAVE; ++q) m = fmax(m, red[q * 9 + t]);
-                unsigned long long *copy = a.part + (size_t)(blockIdx.x % NCOPY) * NWORD;
-                atomicMax(copy + t, (unsigned long long)__double_as_longlong(m));
-            }
-        }
-    }
+    if (MODE == MODE_STAGE) flush_block_maxima(red, a.part + (size_t)(blockIdx.x % NCOPY) * NWORD, wave0);
 }
 
 // ------------------------------------------------------------------------------------------------
