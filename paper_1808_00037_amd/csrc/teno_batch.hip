@@ -443,6 +443,7 @@ teno_status teno_batch_create(const teno_grid *grids, int32_t n, const teno_opts
         if (g.sys != TENO_EULER1D && g.sys != TENO_EULER2D) return TENO_E_UNSUPPORTED;
         if (g.dtype != dtype || g.dtype < 0 || g.dtype > 1) return TENO_E_ARG;
         if (g.nx < 1 || g.ny < 1 || g.nx > (1 << 20) || g.ny > (1 << 20)) return TENO_E_ARG;
+        if ((g.sys == TENO_EULER2D ? 4.0 : 3.0) * g.nx * g.ny >= 2147483647.0) return TENO_E_ARG;
         if (g.sys == TENO_EULER1D && g.ny != 1) return TENO_E_ARG;
         if (g.bc_x < 0 || g.bc_x > 1 || g.bc_y < 0 || g.bc_y > 1) return TENO_E_ARG;
         if (!(g.x1 > g.x0) || !(g.y1 > g.y0)) return TENO_E_ARG;
@@ -482,6 +483,19 @@ teno_status teno_batch_create(const teno_grid *grids, int32_t n, const teno_opts
     }
     b->total = off;
     teno_status st = TENO_OK;
+    // work lists: x-items of the 2D instances, then of the 1D ones; y-items of the 2D instances.
+    // Item counts are launch grid sizes: they must stay below 2^31.
+    {
+        double nx_items = 0.0, ny_items = 0.0;
+        for (int k = 0; k < n; ++k) {
+            nx_items += (double)tiles_x(grids[k], 4);
+            if (grids[k].sys == TENO_EULER2D) ny_items += (double)((grids[k].nx + 3) / 4) * nseg_of(grids[k].ny);
+        }
+        if (nx_items >= 2147483647.0 || ny_items >= 2147483647.0) {
+            delete b;
+            return TENO_E_ARG;
+        }
+    }
     // work lists: x-items of the 2D instances, then of the 1D ones; y-items of the 2D instances
     std::vector<Item> it;
     for (int v = 0; v < 2; ++v) {

@@ -95,3 +95,24 @@ def test_null_arguments(T):
     assert L.teno_rhs(None, None, None, None) == -1
     assert L.teno_run(None, None, 1, 0.0, 0) == -1
     assert L.teno_batch_destroy(None) == -1
+
+
+@pytest.mark.parametrize("bad,code", [(dict(sys=0), -2), (dict(nx=0), -1), (dict(nx=1 << 21), -1),
+                                      (dict(nx=40000, ny=20000), -1), (dict(sys=1, ny=3), -1),
+                                      (dict(dtype=3), -1), (dict(x1=-1.0), -1)])
+def test_batch_create_rejects_invalid_instances(T, bad, code):
+    o = T.Opts()
+    T.lib().teno_default_opts(ctypes.byref(o))
+    grids = (T.Grid * 2)(_grid(T), _grid(T, **bad))
+    h = ctypes.c_void_p(123)
+    assert T.lib().teno_batch_create(grids, 2, ctypes.byref(o), None, ctypes.byref(h)) == code
+    assert h.value is None
+
+
+def test_batch_create_rejects_empty_and_null(T):
+    o = T.Opts()
+    T.lib().teno_default_opts(ctypes.byref(o))
+    grids = (T.Grid * 1)(_grid(T))
+    h = ctypes.c_void_p()
+    assert T.lib().teno_batch_create(grids, 0, ctypes.byref(o), None, ctypes.byref(h)) == -1
+    assert T.lib().teno_batch_create(None, 1, ctypes.byref(o), None, ctypes.byref(h)) == -1
