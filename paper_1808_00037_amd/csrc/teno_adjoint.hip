@@ -81,7 +81,7 @@ static bool adjoint_supported(const teno_ctx *c)
 static teno_status ensure_adj_scratch(teno_ctx *c, int ckpt_every)
 {
     // 3 * ckpt_every stage states of one segment, the running state X, mu and G
-    size_t need = (size_t)(3 * ckpt_every + 3) * c->nelem * sizeof(double);
+    size_t need = ((size_t)3 * (size_t)ckpt_every + 3) * c->nelem * sizeof(double);
     if (c->adj_scratch && c->adj_scratch_bytes >= need) return TENO_OK;
     if (c->adj_scratch) HIP_TRY(hipFree(c->adj_scratch));
     c->adj_scratch = nullptr;
