@@ -339,7 +339,11 @@ def main():
                       "seed": args.seed, "bc": "periodic", "scheme": "TENO7X", "eps": "dx^3", "C_T": 1e-5},
            "roofline": roofline,
            "hbm": {"algorithmic_bytes_per_cell_update": BYTES_PER_CELL_UPDATE,
-                   "achieved_GBps": value * BYTES_PER_CELL_UPDATE, "peak_GBps": PEAK_HBM / 1e9, "frac": hbm_frac},
+                   "achieved_GBps": value * BYTES_PER_CELL_UPDATE, "peak_GBps": PEAK_HBM / 1e9, "frac": hbm_frac,
+                   # the x-stage kernel's HBM bytes per launch measured by rocprofv3 (FETCH_SIZE +
+                   # WRITE_SIZE, calibrated) over its live launch time
+                   "x_stage_measured_GBps": (roofline["traffic"] / (x_ms / 1e3) / 1e9
+                                             if roofline["traffic"] else None)},
            "kernels_ms": {"x_sweep_stage": x_ms, "y_sweep": y_ms, "launches_x": kt["x"][1],
                           "launches_y": kt["y"][1], "eager_ms_per_step": ms_eager / args.steps}}
 
