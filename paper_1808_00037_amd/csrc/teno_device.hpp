@@ -293,13 +293,20 @@ template <typename T> struct Smooth { T b0, b1, b2, tau; };
 template <typename T>
 __device__ __forceinline__ Smooth<T> smooth5(T a, T b, T c, T d, T e)
 {
-    T t0 = a - T(4) * b + T(3) * c, t1 = a - T(2) * b + c;
-    T t2 = b - d, t3 = b - T(2) * c + d;
-    T t4 = T(3) * c - T(4) * d + e, t5 = c - T(2) * d + e;
+    // eq:smooth_expl regrouped: beta_k = p_k^2 + (13/12) u_k^2 with the second differences u_k and
+    // p_k = half the one-sided first differences, which share the u_k:
+    //   p0 = (a - 4b + 3c)/2 = u0/2 + (c - b),  p1 = (b - d)/2,  p2 = (3c - 4d + e)/2 = u2/2 + (c - d)
+    const T u0 = fma(T(-2), b, a) + c;
+    const T u1 = fma(T(-2), c, b) + d;
+    const T u2 = fma(T(-2), d, c) + e;
+    const T p0 = fma(T(0.5), u0, c - b);
+    const T p1 = T(0.5) * (b - d);
+    const T p2 = fma(T(0.5), u2, c - d);
+    constexpr T K = T(13.0 / 12.0);
     Smooth<T> r;
-    r.b0 = T(0.25) * t0 * t0 + T(13.0 / 12.0) * t1 * t1;
-    r.b1 = T(0.25) * t2 * t2 + T(13.0 / 12.0) * t3 * t3;
-    r.b2 = T(0.25) * t4 * t4 + T(13.0 / 12.0) * t5 * t5;
+    r.b0 = fma(K * u0, u0, p0 * p0);
+    r.b1 = fma(K * u1, u1, p1 * p1);
+    r.b2 = fma(K * u2, u2, p2 * p2);
     r.tau = fabs(r.b0 - r.b2);
     return r;
 }
