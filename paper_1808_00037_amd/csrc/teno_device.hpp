@@ -446,8 +446,26 @@ __device__ __forceinline__ void char_basis(const Roe<T> &r, int s, T L[NV], T R[
     }
 }
 
-template <typename T> __device__ __forceinline__ T shfl_up1(T v) { return __shfl_up(v, 1, WAVE); }
-template <typename T> __device__ __forceinline__ T shfl_dn1(T v) { return __shfl_down(v, 1, WAVE); }
+// Neighbour exchange along the wave with the data-parallel-primitive whole-wave shifts (one ALU move
+// per 32-bit word, no LDS traffic): shfl_up1 gives lane k the value of lane k-1 (wave_shr:1),
+// shfl_dn1 the value of lane k+1 (wave_shl:1); the end lane keeps its own value.
+template <int CTRL> __device__ __forceinline__ unsigned dpp_word(unsigned v)
+{
+    return (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, CTRL, 0xf, 0xf, false);
+}
+template <int CTRL> __device__ __forceinline__ double dpp_shift(double v)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = dpp_word<CTRL>((unsigned)b), hi = dpp_word<CTRL>((unsigned)(b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+template <int CTRL> __device__ __forceinline__ float dpp_shift(float v)
+{
+    return __uint_as_float(dpp_word<CTRL>(__float_as_uint(v)));
+}
+template <int CTRL> __device__ __forceinline__ unsigned dpp_shift(unsigned v) { return dpp_word<CTRL>(v); }
+template <typename T> __device__ __forceinline__ T shfl_up1(T v) { return dpp_shift<0x138>(v); }
+template <typename T> __device__ __forceinline__ T shfl_dn1(T v) { return dpp_shift<0x130>(v); }
 
 // ------------------------------------------------------------------------------------------------
 // Sweep kernel arguments.
