@@ -273,6 +273,35 @@ __device__ __forceinline__ int table3(unsigned idx)
     return (int)((w >> (4u * (idx & 15u))) & 15ull);
 }
 
+// The same table indexed in reversed bit order, r = a + 2b + 4c + 8d + 16e, which is how the
+// kernels assemble the neighbour vector (the three flags of a face are stored as delta_0 | delta_1 << 1
+// | delta_2 << 2, so b, c, d land in order with one shift).
+constexpr int reverse5(int x)
+{
+    int r = 0;
+    for (int i = 0; i < 5; ++i)
+        if ((x >> i) & 1) r |= 1 << (4 - i);
+    return r;
+}
+constexpr unsigned long long table3_rev_half(int half)
+{
+    unsigned long long w = 0;
+    for (int j = 0; j < 16; ++j) {
+        const int idx = reverse5(half * 16 + j);
+        const unsigned long long hw = (idx & 16) ? table3_lut_half(1) : table3_lut_half(0);
+        w |= ((hw >> (4 * (idx & 15))) & 15ull) << (4 * j);
+    }
+    return w;
+}
+constexpr unsigned long long LUT_REV_LO = table3_rev_half(0);
+constexpr unsigned long long LUT_REV_HI = table3_rev_half(1);
+
+__device__ __forceinline__ int table3_rev(unsigned r)
+{
+    unsigned long long w = (r & 16u) ? LUT_REV_HI : LUT_REV_LO;
+    return (int)((w >> (4u * (r & 15u))) & 15ull);
+}
+
 // ------------------------------------------------------------------------------------------------
 // Five-point cut-off of one split side (eq:smooth_expl, eq:tau5, eq:TENO1 with C = 1, q = 6,
 // eq:norm, eq:seclect). (a..e) = values at i-2..i+2 in upwind order.
@@ -905,14 +934,12 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
                     fword |= bits << (6 * sf);
                     if (a.scheme == 0) {
                         unsigned left = shfl_up1(bits), right = shfl_dn1(bits);
-                        // Delta+ = (d+_{i-1,0}, d+_{i,0}, d+_{i,1}, d+_{i,2}, d+_{i+1,2})
-                        unsigned ip = ((left & 1u) << 4) | ((dp & 1u) << 3) | ((dp & 2u) << 1) | ((dp & 4u) >> 1)
-                                    | ((right >> 2) & 1u);
-                        // Delta- (mirror) = (d-_{i+1,0}, d-_{i,0}, d-_{i,1}, d-_{i,2}, d-_{i-1,2})
-                        unsigned im = (((right >> 3) & 1u) << 4) | ((dm & 1u) << 3) | ((dm & 2u) << 1)
-                                    | ((dm & 4u) >> 1) | ((left >> 5) & 1u);
-                        mp = table3(ip);
-                        mm = table3(im);
+                        // Delta+ = (d+_{i-1,0}, d+_{i,0}, d+_{i,1}, d+_{i,2}, d+_{i+1,2}) and the mirrored
+                        // Delta- = (d-_{i+1,0}, d-_{i,0}, d-_{i,1}, d-_{i,2}, d-_{i-1,2}), bit-reversed
+                        unsigned ip = (left & 1u) | (dp << 1) | (((right >> 2) & 1u) << 4);
+                        unsigned im = ((right >> 3) & 1u) | (dm << 1) | (((left >> 5) & 1u) << 4);
+                        mp = table3_rev(ip);
+                        mm = table3_rev(im);
                         if (face_ok && (mp == 15 || mm == 15)) bad |= ERR_SELECTION;
                         mp = mp == 15 ? 0 : mp;
                         mm = mm == 15 ? 0 : mm;
