@@ -142,7 +142,7 @@ __global__ void __launch_bounds__(BLOCK, SYS == EULER1D ? 3 : (DIR == 0 ? TENO_M
     const bool wave0 = __builtin_amdgcn_readfirstlane(threadIdx.x) < WAVE;   // wave-uniform
     fill_coef(coef);
     if (MODE == MODE_STAGE && threadIdx.x < BLOCK / WAVE * 9) red[threadIdx.x] = 0.0;   // ordered by the
-    sweep_tile<T, SYS, DIR, false, NSEG, MODE>(a, item.tile, rec, ext, coef, red);        // staging barrier
+    sweep_tile<T, SYS, DIR, false, NSEG, MODE>(a, item.tile, rec, ext, coef, red);        // tile's first barrier
     if (MODE == MODE_STAGE) flush_block_maxima(red, &b.ictrl[item.inst].part[b.ring_next][blockIdx.x % NCOPY_B][0], wave0);
 }
 

@@ -40,6 +40,9 @@ constexpr int SEG_LOAD = 72;    // staged cells per segment (faces c0-1..c0+62 r
 #define TENO_NSEG_X 4
 #endif
 constexpr int NSEG_X = TENO_NSEG_X;  // segments per block, x-sweeps
+#ifndef TENO_X_WAVE_LOCAL
+#define TENO_X_WAVE_LOCAL 1         // x-sweeps order their staging per wave (0: a block barrier)
+#endif
 #ifndef TENO_NSEG_Y
 #define TENO_NSEG_Y 8
 #endif
@@ -123,6 +126,15 @@ __device__ __forceinline__ void lds_barrier()
     asm volatile("" ::: "memory");
     __builtin_amdgcn_s_waitcnt(0xC07F);
     __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
+// Ordering of a wave's own LDS stores before its later LDS loads of other lanes' elements: the
+// wave's LDS operations complete (lgkmcnt 0) and the compiler may not move accesses across.
+__device__ __forceinline__ void wave_lds_fence()
+{
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(0xC07F);
     asm volatile("" ::: "memory");
 }
 
@@ -735,6 +747,11 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
     // spans cells c0-5 .. c0+66 with c0 < len, so for len >= SEG_LOAD one wrap suffices.
     unsigned bad = 0;
     const bool near = a.len >= SEG_LOAD;
+    // x-sweeps: a wave stages exactly the segments it computes, so the only block-wide ordering needed
+    // is that of the caller's coefficient table and maxima slots; it is taken here, before any load
+    // is in flight, and each wave then starts on its segment as soon as its own staging is done
+    constexpr bool WAVE_LOCAL = DIR == 0 && TENO_X_WAVE_LOCAL;
+    if constexpr (WAVE_LOCAL) lds_barrier();
     auto stage_cell = [&](int s, int q, size_t off) {
         T *r = rec + s * SEG_STRIDE + q;
         if constexpr (!EULER) {
@@ -804,7 +821,10 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
             stage_cell(s, q, (size_t)g * a.nx + line);
         }
     }
-    lds_barrier();
+    if constexpr (WAVE_LOCAL)
+        wave_lds_fence();
+    else
+        lds_barrier();
 
     // y-sweeps producing dU/dt leave their results in the segment's own LDS record and store the
     // tile row by row at the end (a lane's cells run down a column: direct stores would be strided)
@@ -1135,7 +1155,7 @@ __global__ void __launch_bounds__(BLOCK, SYS == EULER1D ? 3 : (DIR == 0 ? TENO_M
     fill_coef(coef);
     if (MODE == MODE_STAGE && threadIdx.x < BLOCK / WAVE * 9) red[threadIdx.x] = 0.0;   // ordered by the
     sweep_tile<T, SYS, DIR, FROZEN, NSEG, MODE>(a, xcd_tile(blockIdx.x, gridDim.x), rec, ext, coef,
-                                                red);                                     // staging barrier
+                                                red);                                     // tile's first barrier
     if (MODE == MODE_STAGE) flush_block_maxima(red, a.part + (size_t)(blockIdx.x % NCOPY) * NWORD, wave0);
 }
 
