@@ -47,7 +47,7 @@ def log(*a):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for name in ("teno_device.hpp",):
+    for name in ("teno_device.hpp", "teno_lib.hip"):
         with open(os.path.join(ROOT, "paper_1808_00037_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -1142,10 +1142,16 @@ template <typename T, int SYS, int DIR, int NSEG, int MODE> constexpr int ext_si
 
 // One tile per block (measured faster on MI355X than persistent blocks looping over tiles: freshly
 // scheduled blocks overlap their staging with the compute of resident ones).
-template <typename T, int SYS, int DIR, bool FROZEN, int MODE>
+// REC = false: no selection masks or flags are written (the pointers are known null at compile
+// time, so the mask words are not assembled at all).
+template <typename T, int SYS, int DIR, bool FROZEN, int MODE, bool REC = true>
 __global__ void __launch_bounds__(BLOCK, SYS == EULER1D ? 3 : (DIR == 0 ? TENO_MIN_WAVES_X : TENO_MIN_WAVES_Y))
     sweep_kernel(SweepArgs<T> a)
 {
+    if constexpr (!REC) {
+        a.masks_out = nullptr;
+        a.flags_out = nullptr;
+    }
     constexpr int NSEG = DIR == 0 ? NSEG_X : NSEG_Y;
     __shared__ T rec[NSEG * seg_stride<SYS>()];
     __shared__ __align__(16) T ext[ext_size<T, SYS, DIR, NSEG, MODE>()];

@@ -147,10 +147,16 @@ static void launch_sweep_t(teno_ctx *c, const SweepReq &r)
     std::pair<hipEvent_t, hipEvent_t> *ev = teno_timing_slot(c, DIR);
     if (ev) (void)hipEventRecord(ev->first, c->stream);
     const dim3 grid((unsigned)ntiles);
-    if (r.mode == MODE_RHS)
+    // measured selections that nobody records take the variant without mask output
+    const bool rec = FROZEN || a.masks_out || a.flags_out;
+    if (r.mode == MODE_RHS && rec)
         hipLaunchKernelGGL((sweep_kernel<T, SYS, DIR, FROZEN, MODE_RHS>), grid, dim3(BLOCK), 0, c->stream, a);
-    else if (DIR == 0 && r.mode == MODE_STAGE)
+    else if (r.mode == MODE_RHS)
+        hipLaunchKernelGGL((sweep_kernel<T, SYS, DIR, false, MODE_RHS, false>), grid, dim3(BLOCK), 0, c->stream, a);
+    else if (DIR == 0 && r.mode == MODE_STAGE && rec)
         hipLaunchKernelGGL((sweep_kernel<T, SYS, 0, FROZEN, MODE_STAGE>), grid, dim3(BLOCK), 0, c->stream, a);
+    else if (DIR == 0 && r.mode == MODE_STAGE)
+        hipLaunchKernelGGL((sweep_kernel<T, SYS, 0, false, MODE_STAGE, false>), grid, dim3(BLOCK), 0, c->stream, a);
     else
         hipLaunchKernelGGL((sweep_kernel<T, SYS, DIR, FROZEN, MODE_FACES>), grid, dim3(BLOCK), 0, c->stream, a);
     if (ev) (void)hipEventRecord(ev->second, c->stream);
