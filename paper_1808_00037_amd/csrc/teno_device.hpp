@@ -604,6 +604,30 @@ __device__ __forceinline__ bool cell_primitive_speeds(const T *u, T gamma, T gm1
     }
 }
 
+// The words of the wave-speed record a system with NV conserved variables produces (the second
+// acoustic-free x/y field repeats the first), and their indices packed 4 bits per used slot.
+template <int NV> struct SpeedWords {
+    static constexpr bool use(int q)
+    {
+        return q == 0 || q == 8 || (q == 1 && NV != 1) || (q == 2 && NV == 3) ||
+               ((q == 3 || q == 4 || q == 5 || q == 7) && NV == 4);
+    }
+    static constexpr int count()
+    {
+        int n = 0;
+        for (int q = 0; q < 9; ++q) n += use(q) ? 1 : 0;
+        return n;
+    }
+    static constexpr unsigned pack()
+    {
+        unsigned p = 0;
+        int u = 0;
+        for (int q = 0; q < 9; ++q)
+            if (use(q)) p |= (unsigned)q << (4 * u++);
+        return p;
+    }
+};
+
 // Word q of the wave-speed record (same layout as cell_speeds): 0-3 |lambda| of the x fields,
 // 4-7 of the y fields, 8 the CFL denominator.
 template <int SYS>
@@ -884,13 +908,12 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
             const T al = (T)(sf == 0 ? alv[0] : sf == 1 ? alv[1] : sf == 2 ? alv[2] : alv[3]);
             T Ls[NV], Rs[NV];
             {
-                // computed here for this field only: an opaque copy of the face state keeps the
-                // compiler from hoisting all fields' rows out of the loop (registers held across it
-                // plus copies into place every iteration)
-                Roe<T> rr = roe;
-                asm volatile("" : "+v"(rr.un), "+v"(rr.ut), "+v"(rr.cs), "+v"(rr.ic), "+v"(rr.H), "+v"(rr.q2),
-                                  "+v"(rr.b1), "+v"(rr.b2));
-                char_basis<T, NV>(rr, sf, Ls, Rs);
+                // computed here for this field only: the face state passes through an empty asm
+                // statement that may change it, so the compiler can neither hoist all fields' rows out
+                // of the loop (registers held across it) nor needs copies to keep them in place
+                asm volatile("" : "+v"(roe.un), "+v"(roe.ut), "+v"(roe.cs), "+v"(roe.ic), "+v"(roe.H), "+v"(roe.q2),
+                                  "+v"(roe.b1), "+v"(roe.b2));
+                char_basis<T, NV>(roe, sf, Ls, Rs);
             }
             // the 1/2 of the splitting folded into L (exact scaling)
 #pragma unroll
@@ -1061,32 +1084,68 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
                 }
             }
             if constexpr (MODE == MODE_STAGE) {
-                // this segment's maxima into the wave's LDS slot (the wave owns it: no race); the
-                // words are reduced side by side so that their cross-lane steps interleave
-                constexpr bool USE[9] = {true, NV != 1, NV == 3, NV == 4, NV == 4, NV == 4, false, NV == 4, true};
-                unsigned hi[9], lo[9], mh[9], ml[9];
+                // this segment's maxima into the wave's LDS slots (the wave owns them: no race)
+                constexpr int NU = SpeedWords<NV>::count();
+                constexpr int WSTRIDE = WAVE + 1;          // per word, padded against bank conflicts
+                if constexpr (sizeof(T) == 8 && NU * WSTRIDE <= SEG_STRIDE) {
+                    // Through the segment's own record, which is no longer read: every lane stores its
+                    // words, then lane 8u+j takes the maximum of values j, j+8, .., j+56 of word slot u
+                    // and three row shifts bring the slot's maximum to lane 8u+7. Exact (a maximum of
+                    // doubles), and far fewer instructions than a whole-wave reduction per word.
+                    T *sw = rec + s * SEG_STRIDE;
+                    asm volatile("" ::: "memory");     // after the epilogue's record reads
+                    {
+                        int u = 0;
 #pragma unroll
-                for (int q = 0; q < 9; ++q) {
-                    if (!USE[q]) continue;
-                    const double val = cell_ok ? speed_word<SYS>(q, sx, sy, sc, (double)a.inv_dx, (double)a.inv_dy,
-                                                                 a.alpha_mode) : 0.0;
-                    const unsigned long long b = (unsigned long long)__double_as_longlong(val);
-                    hi[q] = (unsigned)(b >> 32);
-                    lo[q] = (unsigned)b;
-                }
+                        for (int q = 0; q < 9; ++q) {
+                            if (!SpeedWords<NV>::use(q)) continue;
+                            sw[u * WSTRIDE + k] = cell_ok ? speed_word<SYS>(q, sx, sy, sc, (double)a.inv_dx,
+                                                                            (double)a.inv_dy, a.alpha_mode)
+                                                          : 0.0;
+                            ++u;
+                        }
+                    }
+                    wave_lds_fence();
+                    const int u = k >> 3, j = k & 7;
+                    double m = 0.0;
+                    if (u < NU) {
 #pragma unroll
-                for (int q = 0; q < 9; ++q)
-                    if (USE[q]) mh[q] = wave_max_u32(hi[q]);
-#pragma unroll
-                for (int q = 0; q < 9; ++q)
-                    if (USE[q]) ml[q] = wave_max_u32(hi[q] == mh[q] ? lo[q] : 0u);
-#pragma unroll
-                for (int q = 0; q < 9; ++q) {
-                    if (!USE[q]) continue;
-                    const double m = __longlong_as_double((long long)(((unsigned long long)mh[q] << 32) | ml[q]));
-                    if (k == 0) {
+                        for (int i = 0; i < 8; ++i) m = fmax(m, (double)sw[u * WSTRIDE + j + 8 * i]);
+                    }
+                    m = fmax(m, dpp_shift<0x111>(m));  // row_shr:1
+                    m = fmax(m, dpp_shift<0x112>(m));  // row_shr:2
+                    m = fmax(m, dpp_shift<0x114>(m));  // row_shr:4
+                    if (j == 7 && u < NU) {
+                        const int q = (int)((SpeedWords<NV>::pack() >> (4 * u)) & 15u);   // word of slot u
                         red[wid * 9 + q] = fmax(red[wid * 9 + q], m);
                         if (NV == 4 && (q == 1 || q == 5)) red[wid * 9 + q + 1] = fmax(red[wid * 9 + q + 1], m);
+                    }
+                } else {
+                    // the words reduced side by side so that their cross-lane steps interleave
+                    unsigned hi[9], lo[9], mh[9], ml[9];
+#pragma unroll
+                    for (int q = 0; q < 9; ++q) {
+                        if (!SpeedWords<NV>::use(q)) continue;
+                        const double val = cell_ok ? speed_word<SYS>(q, sx, sy, sc, (double)a.inv_dx, (double)a.inv_dy,
+                                                                     a.alpha_mode) : 0.0;
+                        const unsigned long long b = (unsigned long long)__double_as_longlong(val);
+                        hi[q] = (unsigned)(b >> 32);
+                        lo[q] = (unsigned)b;
+                    }
+#pragma unroll
+                    for (int q = 0; q < 9; ++q)
+                        if (SpeedWords<NV>::use(q)) mh[q] = wave_max_u32(hi[q]);
+#pragma unroll
+                    for (int q = 0; q < 9; ++q)
+                        if (SpeedWords<NV>::use(q)) ml[q] = wave_max_u32(hi[q] == mh[q] ? lo[q] : 0u);
+#pragma unroll
+                    for (int q = 0; q < 9; ++q) {
+                        if (!SpeedWords<NV>::use(q)) continue;
+                        const double m = __longlong_as_double((long long)(((unsigned long long)mh[q] << 32) | ml[q]));
+                        if (k == 0) {
+                            red[wid * 9 + q] = fmax(red[wid * 9 + q], m);
+                            if (NV == 4 && (q == 1 || q == 5)) red[wid * 9 + q + 1] = fmax(red[wid * 9 + q + 1], m);
+                        }
                     }
                 }
             }
