@@ -447,15 +447,19 @@ template <typename T> struct Roe {
 // Left eigenvector (row s of L) and right eigenvector (column s of R) of the flux Jacobian at the
 // Roe state, in local variable order (rho, m_n, [m_t], E). Fields: u_n - c, u_n (entropy),
 // [u_n (shear)], u_n + c. With b1 = (gamma-1)/c^2 and b2 = b1 |u|^2 / 2, L R = I.
-// Scalar systems: L = R = 1.
-template <typename T, int NV>
+// LS scales the row by LS (a power of two, so the scaled row is exactly LS times the plain one);
+// the sweeps take LS = 1/2, the half of the flux splitting, folded into each row's own constants.
+// Scalar systems: L = LS, R = 1.
+template <typename T, int NV, int LSINV = 1>
 __device__ __forceinline__ void char_basis(const Roe<T> &r, int s, T L[NV], T R[NV])
 {
+    static_assert(LSINV == 1 || LSINV == 2, "row scale 1 or 1/2");
+    constexpr T LS = T(1) / T(LSINV);
     if constexpr (NV == 1) {
-        L[0] = T(1);
+        L[0] = LS;
         R[0] = T(1);
     } else {
-        const T h = T(0.5);
+        const T h = T(0.5) * LS;
         // map the 1D fields (0, 1, 2) onto the 2D ones (0, 1, 3)
         const int s4 = (NV == 3 && s == 2) ? 3 : s;
         T l0, l1, l2 = T(0), l3, r0, r1, r2 = T(0), r3;
@@ -464,12 +468,14 @@ __device__ __forceinline__ void char_basis(const Roe<T> &r, int s, T L[NV], T R[
             l0 = h * (r.b2 + r.un * r.ic); l1 = -h * (r.b1 * r.un + r.ic); l2 = -h * r.b1 * r.ut; l3 = h * r.b1;
             r0 = T(1); r1 = r.un - r.cs; r2 = r.ut; r3 = r.H - r.un * r.cs;
             break;
-        case 1:
-            l0 = T(1) - r.b2; l1 = r.b1 * r.un; l2 = r.b1 * r.ut; l3 = -r.b1;
-            r0 = T(1); r1 = r.un; r2 = r.ut; r3 = h * r.q2;
+        case 1: {
+            const T t = LS * r.b1;
+            l0 = fma(-LS, r.b2, LS); l1 = t * r.un; l2 = t * r.ut; l3 = -t;
+            r0 = T(1); r1 = r.un; r2 = r.ut; r3 = T(0.5) * r.q2;
             break;
+        }
         case 2:
-            l0 = -r.ut; l1 = T(0); l2 = T(1); l3 = T(0);
+            l0 = -LS * r.ut; l1 = T(0); l2 = LS; l3 = T(0);
             r0 = T(0); r1 = T(0); r2 = T(1); r3 = r.ut;
             break;
         default:
@@ -913,11 +919,8 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
                 // of the loop (registers held across it) nor needs copies to keep them in place
                 asm volatile("" : "+v"(roe.un), "+v"(roe.ut), "+v"(roe.cs), "+v"(roe.ic), "+v"(roe.H), "+v"(roe.q2),
                                   "+v"(roe.b1), "+v"(roe.b2));
-                char_basis<T, NV>(roe, sf, Ls, Rs);
+                char_basis<T, NV, 2>(roe, sf, Ls, Rs);       // L/2: the 1/2 of the splitting
             }
-            // the 1/2 of the splitting folded into L (exact scaling)
-#pragma unroll
-            for (int v = 0; v < NV; ++v) Ls[v] *= T(0.5);
             T vp[8], vm[8];
             if (NV == 4 && sf == 2) {
                 // shear field: L_2 = (-u_t, 0, 1, 0), so L_2 U = m_t - u_t rho and L_2 F = u_n L_2 U
