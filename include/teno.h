@@ -187,11 +187,19 @@ size_t teno_batch_total_elems(const teno_batch *b);
 size_t teno_batch_offset(const teno_batch *b, int32_t k);
 
 /* Advance every instance by nsteps SSP-RK3 steps (each instance with its own CFL dt).
- * mode 0: all instances per kernel in persistent work-queue launches, the step captured once in
- * a HIP graph and replayed; mode 1: one launch per instance per kernel (reference form).
+ * mode 0: all instances per kernel in static work-list launches (one (instance, tile) item per
+ * block), the whole run captured once in a HIP graph and replayed; mode 1: one launch per
+ * instance per kernel (reference form).
  * U_dev: the packed state of teno_batch_total_elems() elements. Both modes give bitwise equal
  * results. */
 teno_status teno_batch_run(teno_batch *b, void *U_dev, int32_t nsteps, int32_t mode);
+
+/* Fix mode 0's launch shape instead of letting the first mode-0 run pick it by timing:
+ * x_tile segments per x-sweep block and y_tile columns per y-sweep block (4 or 8 each), and
+ * packed = 1 to give the short ragged last segments of 2D instances' lines to tail launches that
+ * take several lines per wave (0: every segment in the main launches). The result does not depend
+ * on the shape. Host-only; TENO_E_ARG for other values or a null batch. Discards a captured graph. */
+teno_status teno_batch_set_shape(teno_batch *b, int32_t x_tile, int32_t y_tile, int32_t packed);
 
 /* Synchronise and return (then clear) the batch's sticky device error status. */
 teno_status teno_batch_poll(teno_batch *b);

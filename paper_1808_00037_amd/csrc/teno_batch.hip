@@ -39,6 +39,7 @@ constexpr int WS_CHUNK = 8192;      // cells per wave-speed work item
 
 struct BatchInst {
     int sys, nx, ny, bc_x, bc_y;
+    int pack_x, pack_y;             // ragged last segments packed (2D instances with short tails)
     int pad_;
     long long off;                  // element offset of the instance in the packed buffers
     double inv_dx, inv_dy, eps_x, eps_y;
@@ -65,21 +66,21 @@ template <typename T> struct BatchSweep {
     T *out;                         // dU/dt (y) or the next stage (x)
     unsigned *err;
     int mode, stage, ring_next, scheme, alpha_mode;
+    int packed;                     // the item lists leave packable ragged segments to the tail items
     T ct, gamma;
     T smooth_k;                     // all-smooth shortcut factor for ct
 };
 
 int nseg_of(int len) { return (len + SEG_CELLS - 1) / SEG_CELLS; }
 
+// Whether a 2D instance's ragged last segments along a sweep (line length len, nlines lines) are
+// packed several lines to a wave: at least two pieces fit and there are lines to share a wave.
+__host__ __device__ inline bool packable(int len, int nlines) { return nlines > 1 && tail_geom(len).P >= 2; }
+
 int tiles_x(const teno_grid &g, int nseg_x)
 {
     long long segs = (long long)nseg_of(g.nx) * g.ny;
     return (int)((segs + nseg_x - 1) / nseg_x);
-}
-
-int tiles_y(const teno_grid &g, int nseg_y)
-{
-    return ((g.nx + nseg_y - 1) / nseg_y) * nseg_of(g.ny);
 }
 
 }  // namespace
@@ -106,6 +107,7 @@ __device__ __forceinline__ SweepArgs<T> item_args(const BatchSweep<T> &b, const 
     a.len = DIR == 0 ? I.nx : I.ny;
     a.nlines = DIR == 0 ? I.ny : I.nx;
     a.nseg = (a.len + SEG_CELLS - 1) / SEG_CELLS;
+    if (b.packed && (DIR == 0 ? I.pack_x : I.pack_y)) a.nseg -= 1;   // the last one is a tail item's
     a.bc = DIR == 0 ? I.bc_x : I.bc_y;
     a.bc_other = 0;
     a.mode = b.mode;
@@ -127,7 +129,8 @@ __device__ __forceinline__ SweepArgs<T> item_args(const BatchSweep<T> &b, const 
 // One (instance, tile) item per block. y-sweeps produce the y-part of dU/dt (MODE_RHS); x-sweeps
 // apply the RK stage (MODE_STAGE) and put the block's wave-speed maxima into one spread copy of the
 // instance's next ring slot. The grid is exactly the item range [begin, end).
-template <typename T, int SYS, int DIR, int NSEG>
+// PACK: tail items, each the ragged last segments of NSEG x P lines of one instance (P per wave).
+template <typename T, int SYS, int DIR, int NSEG, bool PACK>
 __global__ void __launch_bounds__(BLOCK, SYS == EULER1D ? 3 : (DIR == 0 ? TENO_MIN_WAVES_X : TENO_MIN_WAVES_Y))
     batch_sweep_kernel(BatchSweep<T> b)
 {
@@ -142,7 +145,7 @@ __global__ void __launch_bounds__(BLOCK, SYS == EULER1D ? 3 : (DIR == 0 ? TENO_M
     const bool wave0 = __builtin_amdgcn_readfirstlane(threadIdx.x) < WAVE;   // wave-uniform
     fill_coef(coef);
     if (MODE == MODE_STAGE && threadIdx.x < BLOCK / WAVE * 9) red[threadIdx.x] = 0.0;   // ordered by the
-    sweep_tile<T, SYS, DIR, false, NSEG, MODE>(a, item.tile, rec, ext, coef, red);        // tile's first barrier
+    sweep_tile<T, SYS, DIR, false, NSEG, MODE, PACK>(a, item.tile, rec, ext, coef, red);  // tile's first barrier
     if (MODE == MODE_STAGE) flush_block_maxima(red, &b.ictrl[item.inst].part[b.ring_next][blockIdx.x % NCOPY_B][0], wave0);
 }
 
@@ -229,16 +232,19 @@ struct teno_batch {
     InstCtrl *ictrl_d = nullptr;
     unsigned *err_d = nullptr;
     void *S1 = nullptr, *S2 = nullptr, *dUy = nullptr;
-    // work lists, one per tile-shape variant (index 0: 4 segments, 1: 8 segments per tile). The
-    // x-list holds the 2D instances' items first (ending at x2_end), then the 1D instances'.
-    Item *items_x_d[2] = {nullptr, nullptr}, *items_y_d[2] = {nullptr, nullptr};
-    std::vector<int> xb[2], xe[2], yb[2], ye[2];      // per-instance item ranges
-    int x2_end[2] = {0, 0}, x_total[2] = {0, 0}, y_total[2] = {0, 0};
+    // work lists, one per tile-shape variant v (0: 4 segments, 1: 8 segments per tile) and layout p
+    // (0: plain, every segment a main item; 1: packable ragged segments as tail items). The x-list
+    // holds the 2D instances' main items [0, x2m_end), their tail items [x2m_end, x2_end), then the
+    // 1D instances' items; the y-list the main items [0, ym_end), then the tail items.
+    Item *items_x_d[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    Item *items_y_d[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    std::vector<int> xb[2], xe[2], yb[2], ye[2];      // per-instance item ranges of the plain lists
+    int x2m_end[2][2] = {}, x2_end[2][2] = {}, x_total[2][2] = {}, ym_end[2][2] = {}, y_total[2][2] = {};
     Item *items_w_d = nullptr;
     std::vector<int> begin_w;
     // tuned launch shape
     bool tuned = false;
-    int vx = 0, vy = 1;
+    int vx = 0, vy = 1, pk = 1;
     // captured run (a second stream for the parallel branch of the 1D instances)
     hipStream_t cap_stream = nullptr, cap_stream2 = nullptr;
     hipEvent_t ev_fork[3] = {nullptr, nullptr, nullptr}, ev_join[3] = {nullptr, nullptr, nullptr};
@@ -266,30 +272,36 @@ BatchSweep<T> base_args(const teno_batch *b)
     return a;
 }
 
-template <typename T, int SYS, int DIR>
+template <typename T, int SYS, int DIR, bool PACK = false>
 void launch_batch_sweep(hipStream_t s, int variant, const BatchSweep<T> &a)
 {
     const int grid = a.end - a.begin;
     if (grid <= 0) return;
     if (variant == 0)
-        hipLaunchKernelGGL((batch_sweep_kernel<T, SYS, DIR, 4>), dim3(grid), dim3(BLOCK), 0, s, a);
+        hipLaunchKernelGGL((batch_sweep_kernel<T, SYS, DIR, 4, PACK>), dim3(grid), dim3(BLOCK), 0, s, a);
     else
-        hipLaunchKernelGGL((batch_sweep_kernel<T, SYS, DIR, 8>), dim3(grid), dim3(BLOCK), 0, s, a);
+        hipLaunchKernelGGL((batch_sweep_kernel<T, SYS, DIR, 8, PACK>), dim3(grid), dim3(BLOCK), 0, s, a);
 }
 
-// Item ranges of one launch group: y-items, 2D x-items, 1D x-items.
+// Item ranges of one launch group in the lists of layout p: y main and tail items, 2D x main and
+// tail items, 1D x-items.
 struct Ranges {
-    int y0, y1, x2a, x2b, x1a, x1b;
+    int p;
+    int y0, y1, yt0, yt1, x2a, x2b, x2ta, x2tb, x1a, x1b;
 };
 
-Ranges all_ranges(const teno_batch *b, int vx, int vy)
+Ranges all_ranges(const teno_batch *b, int vx, int vy, int p)
 {
-    return {0, b->y_total[vy], 0, b->x2_end[vx], b->x2_end[vx], b->x_total[vx]};
+    return {p,
+            0, b->ym_end[vy][p], b->ym_end[vy][p], b->y_total[vy][p],
+            0, b->x2m_end[vx][p], b->x2m_end[vx][p], b->x2_end[vx][p],
+            b->x2_end[vx][p], b->x_total[vx][p]};
 }
 
+// one instance's items in the plain lists
 Ranges instance_ranges(const teno_batch *b, int k, int vx, int vy)
 {
-    Ranges r{b->yb[vy][k], b->ye[vy][k], 0, 0, 0, 0};
+    Ranges r{0, b->yb[vy][k], b->ye[vy][k], 0, 0, 0, 0, 0, 0, 0, 0};
     if (b->inst[k].sys == EULER2D) {
         r.x2a = b->xb[vx][k];
         r.x2b = b->xe[vx][k];
@@ -313,15 +325,19 @@ void enqueue_step(teno_batch *b, hipStream_t s, T *U, int first, int count, cons
         hipLaunchKernelGGL(batch_prep_kernel, dim3(count < 1024 ? count : 1024), dim3(64), 0, s, b->ictrl_d, first,
                            count, k, k, b->opts.cfl, b->err_d);
         BatchSweep<T> a = base_args<T>(b);
+        a.packed = r.p;
         a.stage = k;
         a.U = in[k];
-        a.items = b->items_y_d[vy];
+        a.items = b->items_y_d[vy][r.p];
         a.begin = r.y0;
         a.end = r.y1;
         a.mode = MODE_RHS;
         a.out = (T *)b->dUy;
         launch_batch_sweep<T, EULER2D, 1>(s, vy, a);
-        a.items = b->items_x_d[vx];
+        a.begin = r.yt0;
+        a.end = r.yt1;
+        launch_batch_sweep<T, EULER2D, 1, true>(s, vy, a);
+        a.items = b->items_x_d[vx][r.p];
         a.mode = MODE_STAGE;
         a.U0 = U;
         a.addend = (T *)b->dUy;
@@ -340,6 +356,9 @@ void enqueue_step(teno_batch *b, hipStream_t s, T *U, int first, int count, cons
         a.begin = r.x2a;
         a.end = r.x2b;
         launch_batch_sweep<T, EULER2D, 0>(s, vx, a);
+        a.begin = r.x2ta;
+        a.end = r.x2tb;
+        launch_batch_sweep<T, EULER2D, 0, true>(s, vx, a);
         if (fork) {
             (void)hipStreamWaitEvent(s, b->ev_join[k], 0);
         } else {
@@ -381,25 +400,27 @@ teno_status run_t(teno_batch *b, T *U, int nsteps, int mode)
         HIP_TRY(hipEventCreate(&e0));
         HIP_TRY(hipEventCreate(&e1));
         float best = 1e30f;
-        int bvx = 0, bvy = 1;
-        for (int vx = 0; vx < 2; ++vx)
-            for (int vy = 0; vy < 2; ++vy) {
-                const Ranges r = all_ranges(b, vx, vy);
-                enqueue_init<T>(b, b->stream, tmp, 0, b->n);
-                enqueue_step<T>(b, b->stream, tmp, 0, b->n, r, vx, vy);    // warm-up
-                HIP_TRY(hipEventRecord(e0, b->stream));
-                enqueue_step<T>(b, b->stream, tmp, 0, b->n, r, vx, vy);
-                HIP_TRY(hipEventRecord(e1, b->stream));
-                HIP_TRY(hipEventSynchronize(e1));
-                float ms = 0.f;
-                HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-                if (ms < best) { best = ms; bvx = vx; bvy = vy; }
-            }
+        int bvx = 0, bvy = 1, bp = 0;
+        for (int p = 0; p < 2; ++p)
+            for (int vx = 0; vx < 2; ++vx)
+                for (int vy = 0; vy < 2; ++vy) {
+                    const Ranges r = all_ranges(b, vx, vy, p);
+                    enqueue_init<T>(b, b->stream, tmp, 0, b->n);
+                    enqueue_step<T>(b, b->stream, tmp, 0, b->n, r, vx, vy);    // warm-up
+                    HIP_TRY(hipEventRecord(e0, b->stream));
+                    enqueue_step<T>(b, b->stream, tmp, 0, b->n, r, vx, vy);
+                    HIP_TRY(hipEventRecord(e1, b->stream));
+                    HIP_TRY(hipEventSynchronize(e1));
+                    float ms = 0.f;
+                    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+                    if (ms < best) { best = ms; bvx = vx; bvy = vy; bp = p; }
+                }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         HIP_TRY(hipFree(tmp));
         b->vx = bvx;
         b->vy = bvy;
+        b->pk = bp;
         b->tuned = true;
         unsigned z = 0;     // the tuning run's state is discarded, and so is its status
         HIP_TRY(hipMemcpy(b->err_d, &z, sizeof z, hipMemcpyHostToDevice));
@@ -417,7 +438,7 @@ teno_status run_t(teno_batch *b, T *U, int nsteps, int mode)
         }
         HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
         enqueue_init<T>(b, b->cap_stream, U, 0, b->n);
-        const Ranges r = all_ranges(b, b->vx, b->vy);
+        const Ranges r = all_ranges(b, b->vx, b->vy, b->pk);
         for (int n = 0; n < nsteps; ++n)
             enqueue_step<T>(b, b->cap_stream, U, 0, b->n, r, b->vx, b->vy, b->cap_stream2);
         HIP_TRY(hipStreamEndCapture(b->cap_stream, &b->graph));
@@ -470,6 +491,8 @@ teno_status teno_batch_create(const teno_grid *grids, int32_t n, const teno_opts
         I.ny = g.ny;
         I.bc_x = g.bc_x;
         I.bc_y = g.bc_y;
+        I.pack_x = g.sys == TENO_EULER2D && packable(g.nx, g.ny);
+        I.pack_y = g.sys == TENO_EULER2D && packable(g.ny, g.nx);
         I.off = (long long)off;
         double dx = (g.x1 - g.x0) / g.nx, dy = (g.y1 - g.y0) / g.ny;
         I.inv_dx = 1.0 / dx;
@@ -491,12 +514,14 @@ teno_status teno_batch_create(const teno_grid *grids, int32_t n, const teno_opts
             nx_items += (double)tiles_x(grids[k], 4);
             if (grids[k].sys == TENO_EULER2D) ny_items += (double)((grids[k].nx + 3) / 4) * nseg_of(grids[k].ny);
         }
-        if (nx_items >= 2147483647.0 || ny_items >= 2147483647.0) {
+        // (the packed lists hold at most one more item per instance)
+        if (nx_items + n >= 2147483647.0 || ny_items + n >= 2147483647.0) {
             delete b;
             return TENO_E_ARG;
         }
     }
-    // work lists: x-items of the 2D instances, then of the 1D ones; y-items of the 2D instances
+    // work lists (see teno_batch): per tile shape v and layout p, x-items of the 2D instances (main,
+    // then tail), then of the 1D ones; y-items of the 2D instances (main, then tail)
     std::vector<Item> it;
     for (int v = 0; v < 2; ++v) {
         const int ns = v == 0 ? 4 : 8;
@@ -504,36 +529,60 @@ teno_status teno_batch_create(const teno_grid *grids, int32_t n, const teno_opts
         b->xe[v].assign(n, 0);
         b->yb[v].assign(n, 0);
         b->ye[v].assign(n, 0);
-        it.clear();
-        for (int pass = 0; pass < 2; ++pass) {
-            for (int k = 0; k < n; ++k) {
-                if ((grids[k].sys == TENO_EULER2D) != (pass == 0)) continue;
-                b->xb[v][k] = (int)it.size();
-                int t = tiles_x(grids[k], ns);
+        for (int p = 0; p < 2; ++p) {
+            it.clear();
+            for (int k = 0; k < n; ++k) {                       // 2D main items
+                if (grids[k].sys != TENO_EULER2D) continue;
+                const bool pk = p == 1 && b->inst[k].pack_x;
+                const long long segs = (long long)(nseg_of(grids[k].nx) - (pk ? 1 : 0)) * grids[k].ny;
+                const int t = (int)((segs + ns - 1) / ns);
+                if (p == 0) b->xb[v][k] = (int)it.size();
                 for (int q = 0; q < t; ++q) it.push_back({k, q});
-                b->xe[v][k] = (int)it.size();
+                if (p == 0) b->xe[v][k] = (int)it.size();
             }
-            if (pass == 0) b->x2_end[v] = (int)it.size();
-        }
-        b->x_total[v] = (int)it.size();
-        if (hipMalloc(&b->items_x_d[v], (it.size() + 1) * sizeof(Item)) != hipSuccess ||
-            (it.size() && hipMemcpy(b->items_x_d[v], it.data(), it.size() * sizeof(Item), hipMemcpyHostToDevice) !=
-                              hipSuccess))
-            st = TENO_E_HIP;
-        it.clear();
-        for (int k = 0; k < n; ++k) {
-            b->yb[v][k] = (int)it.size();
-            if (grids[k].sys == TENO_EULER2D) {
-                int t = tiles_y(grids[k], ns);
+            b->x2m_end[v][p] = (int)it.size();
+            for (int k = 0; k < n && p == 1; ++k) {             // 2D tail items
+                if (grids[k].sys != TENO_EULER2D || !b->inst[k].pack_x) continue;
+                const int per = ns * tail_geom(grids[k].nx).P;   // lines per tail item
+                const int t = (grids[k].ny + per - 1) / per;
                 for (int q = 0; q < t; ++q) it.push_back({k, q});
             }
-            b->ye[v][k] = (int)it.size();
+            b->x2_end[v][p] = (int)it.size();
+            for (int k = 0; k < n; ++k) {                       // 1D items
+                if (grids[k].sys == TENO_EULER2D) continue;
+                const int t = tiles_x(grids[k], ns);
+                if (p == 0) b->xb[v][k] = (int)it.size();
+                for (int q = 0; q < t; ++q) it.push_back({k, q});
+                if (p == 0) b->xe[v][k] = (int)it.size();
+            }
+            b->x_total[v][p] = (int)it.size();
+            if (hipMalloc(&b->items_x_d[v][p], (it.size() + 1) * sizeof(Item)) != hipSuccess ||
+                (it.size() &&
+                 hipMemcpy(b->items_x_d[v][p], it.data(), it.size() * sizeof(Item), hipMemcpyHostToDevice) != hipSuccess))
+                st = TENO_E_HIP;
+            it.clear();
+            for (int k = 0; k < n; ++k) {                       // y main items
+                if (p == 0) b->yb[v][k] = (int)it.size();
+                if (grids[k].sys == TENO_EULER2D) {
+                    const bool pk = p == 1 && b->inst[k].pack_y;
+                    const int t = ((grids[k].nx + ns - 1) / ns) * (nseg_of(grids[k].ny) - (pk ? 1 : 0));
+                    for (int q = 0; q < t; ++q) it.push_back({k, q});
+                }
+                if (p == 0) b->ye[v][k] = (int)it.size();
+            }
+            b->ym_end[v][p] = (int)it.size();
+            for (int k = 0; k < n && p == 1; ++k) {             // y tail items
+                if (grids[k].sys != TENO_EULER2D || !b->inst[k].pack_y) continue;
+                const int per = ns * tail_geom(grids[k].ny).P;
+                const int t = (grids[k].nx + per - 1) / per;
+                for (int q = 0; q < t; ++q) it.push_back({k, q});
+            }
+            b->y_total[v][p] = (int)it.size();
+            if (hipMalloc(&b->items_y_d[v][p], (it.size() + 1) * sizeof(Item)) != hipSuccess ||
+                (it.size() &&
+                 hipMemcpy(b->items_y_d[v][p], it.data(), it.size() * sizeof(Item), hipMemcpyHostToDevice) != hipSuccess))
+                st = TENO_E_HIP;
         }
-        b->y_total[v] = (int)it.size();
-        if (hipMalloc(&b->items_y_d[v], (it.size() + 1) * sizeof(Item)) != hipSuccess ||
-            (it.size() && hipMemcpy(b->items_y_d[v], it.data(), it.size() * sizeof(Item), hipMemcpyHostToDevice) !=
-                              hipSuccess))
-            st = TENO_E_HIP;
     }
     it.clear();
     b->begin_w.assign(1, 0);
@@ -577,10 +626,11 @@ teno_status teno_batch_destroy(teno_batch *b)
         if (b->ev_fork[k]) (void)hipEventDestroy(b->ev_fork[k]);
         if (b->ev_join[k]) (void)hipEventDestroy(b->ev_join[k]);
     }
-    for (int v = 0; v < 2; ++v) {
-        (void)hipFree(b->items_x_d[v]);
-        (void)hipFree(b->items_y_d[v]);
-    }
+    for (int v = 0; v < 2; ++v)
+        for (int p = 0; p < 2; ++p) {
+            (void)hipFree(b->items_x_d[v][p]);
+            (void)hipFree(b->items_y_d[v][p]);
+        }
     (void)hipFree(b->items_w_d);
     (void)hipFree(b->inst_d);
     (void)hipFree(b->ictrl_d);
@@ -589,6 +639,18 @@ teno_status teno_batch_destroy(teno_batch *b)
     (void)hipFree(b->S2);
     (void)hipFree(b->dUy);
     delete b;
+    return TENO_OK;
+}
+
+teno_status teno_batch_set_shape(teno_batch *b, int32_t x_tile, int32_t y_tile, int32_t packed)
+{
+    if (!b || (x_tile != 4 && x_tile != 8) || (y_tile != 4 && y_tile != 8) || (packed != 0 && packed != 1))
+        return TENO_E_ARG;
+    b->vx = x_tile == 4 ? 0 : 1;
+    b->vy = y_tile == 4 ? 0 : 1;
+    b->pk = packed;
+    b->tuned = true;
+    b->graph_steps = -1;            // recapture at the next mode-0 run
     return TENO_OK;
 }
 

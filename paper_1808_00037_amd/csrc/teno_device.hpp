@@ -27,6 +27,11 @@
 
 namespace teno {
 
+// Multiply-adds are fused only within one expression, as written (no fusion across statements): the
+// rounding of every result then follows the source alone, whatever kernel variant inlines the code,
+// so that all launch shapes of a sweep give bitwise equal results.
+#pragma clang fp contract(on)
+
 enum : int { ADV1D = 0, EULER1D = 1, EULER2D = 2, BURGERS1D = 3 };
 enum : int { MODE_RHS = 0, MODE_STAGE = 1, MODE_FACES = 2 };
 enum : unsigned { ERR_NONFINITE = 1u, ERR_NONPHYSICAL = 2u, ERR_SELECTION = 4u };
@@ -36,6 +41,28 @@ constexpr int BLOCK = 256;
 constexpr int SEG_CELLS = 61;   // cells finished per segment
 constexpr int SEG_HALO = 5;     // first staged cell is c0 - 5
 constexpr int SEG_LOAD = 72;    // staged cells per segment (faces c0-1..c0+62 read c0-5..c0+65)
+
+// Packed ragged segments. The last segment of a line holds nt = len - c0 cells (c0 its first cell).
+// When nt is short, one wave can take that segment of P lines at once: piece i of the wave stages
+// cells c0-5 .. c0+nt+4 of its line at record positions [i W, (i+1) W), W = nt + 10, and lane
+// i W + kl then computes face c0-1+kl of that line (kl = 0 .. nt+2 are the faces the piece's cells
+// and their neighbour vectors need; the other lanes of the piece straddle two lines and are idle).
+// The last piece's lanes must stay below 64: P W <= 71.
+constexpr int PACK_GAP = 10;
+constexpr int PACK_SPAN = 71;
+struct TailGeom {
+    int c0, nt, W, P;
+};
+__host__ __device__ inline TailGeom tail_geom(int len)
+{
+    TailGeom g;
+    const int nseg = (len + SEG_CELLS - 1) / SEG_CELLS;
+    g.c0 = (nseg - 1) * SEG_CELLS;
+    g.nt = len - g.c0;
+    g.W = g.nt + PACK_GAP;
+    g.P = PACK_SPAN / g.W;
+    return g;
+}
 #ifndef TENO_NSEG_X
 #define TENO_NSEG_X 4
 #endif
@@ -736,10 +763,12 @@ template <typename T> __device__ __forceinline__ void fill_coef(T *coef)
 // maxima of the produced cells into red (per-wave slots).
 // ext (x-sweeps with an RK stage or a y-part): LDS for the epilogue operands of the owned cells,
 // [NSEG][2][NV][WAVE] (U^n, then the y-part of dU/dt), loaded with the tile.
-template <typename T, int SYS, int DIR, bool FROZEN, int NSEG, int MODE>
+template <typename T, int SYS, int DIR, bool FROZEN, int NSEG, int MODE, bool PACK = false>
 __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *rec, T *ext, const T *coef,
                                            double *red)
 {
+    static_assert(!PACK || (SYS == EULER2D && !FROZEN && MODE != MODE_FACES),
+                  "packed ragged segments: 2D Euler sweeps without recorded selections");
     constexpr int NV = Sys<SYS>::NV;
     constexpr int SEG_STRIDE = seg_stride<SYS>();
     constexpr bool EULER = SYS == EULER1D || SYS == EULER2D;
@@ -762,6 +791,19 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
             if (line >= a.nlines) line = -1;
         }
     };
+
+    // packed ragged segments (PACK): the tile's lines start at pk_l0; piece i of segment s is line
+    // pk_l0 + i NSEG + s; lane k belongs to piece (k pk_M) >> 16 (exact division by W for k < 72)
+    int pk_c0 = 0, pk_nt = 0, pk_W = 1, pk_P = 1, pk_M = 0, pk_l0 = 0;
+    if constexpr (PACK) {
+        const TailGeom tg = tail_geom(a.len);
+        pk_c0 = tg.c0;
+        pk_nt = tg.nt;
+        pk_W = tg.W;
+        pk_P = tg.P;
+        pk_M = 65536 / pk_W + 1;
+        pk_l0 = tile * NSEG * pk_P;
+    }
 
     // Lax-Friedrichs constants of this direction and the stage's dt, read before any background copy
     // is issued (vector-memory completions are waited for in order) and kept in scalar registers
@@ -811,8 +853,33 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
     };
     // epilogue operands of the owned cells (lanes 1..61), staged with the tile so that their
     // latency overlaps the staging instead of the end of the face computation
-    constexpr bool HAS_EXT = DIR == 0 && MODE != MODE_FACES;
-    if constexpr (DIR == 0) {
+    constexpr bool HAS_EXT = DIR == 0 && MODE != MODE_FACES && !PACK;
+    if constexpr (PACK && DIR == 0) {
+        for (int s = __builtin_amdgcn_readfirstlane(wid); s < NSEG; s += BLOCK / WAVE) {
+            const int line0 = pk_l0 + s;                 // piece 0: the wave has no line if absent
+            if (line0 >= a.nlines) continue;             // wave-uniform
+            for (int q = lane; q < SEG_LOAD; q += WAVE) {
+                const int i = (q * pk_M) >> 16, ql = q - i * pk_W;
+                int line = pk_l0 + i * NSEG + s;
+                if (i >= pk_P || line >= a.nlines) line = line0;   // idle positions: any valid cell
+                const int g = near ? bc_index_near(pk_c0 - SEG_HALO + ql, a.len, a.bc)
+                                   : bc_index(pk_c0 - SEG_HALO + ql, a.len, a.bc);
+                stage_cell(s, q, (size_t)line * a.nx + g);
+            }
+        }
+    } else if constexpr (PACK) {
+        for (int idx = tid; idx < NSEG * SEG_LOAD; idx += BLOCK) {
+            const int s = idx % NSEG, q = idx / NSEG;
+            const int line0 = pk_l0 + s;
+            if (line0 >= a.nlines) continue;
+            const int i = (q * pk_M) >> 16, ql = q - i * pk_W;
+            int line = pk_l0 + i * NSEG + s;
+            if (i >= pk_P || line >= a.nlines) line = line0;
+            const int g = near ? bc_index_near(pk_c0 - SEG_HALO + ql, a.len, a.bc)
+                               : bc_index(pk_c0 - SEG_HALO + ql, a.len, a.bc);
+            stage_cell(s, q, (size_t)g * a.nx + line);
+        }
+    } else if constexpr (DIR == 0) {
         for (int s = __builtin_amdgcn_readfirstlane(wid); s < NSEG; s += BLOCK / WAVE) {
             int line, c0;
             seg_of(s, line, c0);
@@ -859,18 +926,34 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
     // y-sweeps producing dU/dt leave their results in the segment's own LDS record and store the
     // tile row by row at the end (a lane's cells run down a column: direct stores would be strided)
     constexpr bool STAGE_OUT = DIR == 1 && MODE == MODE_RHS;
-    static_assert(NV * SEG_CELLS <= SEG_STRIDE, "staged output must fit in a segment record");
+    constexpr int OUTW = PACK ? WAVE : SEG_CELLS;   // staged output per variable
+    static_assert(NV * OUTW <= SEG_STRIDE, "staged output must fit in a segment record");
 
     // the segment loop is wave-uniform: keep its indices in scalar registers
     for (int s = __builtin_amdgcn_readfirstlane(wid); s < NSEG; s += BLOCK / WAVE) {
         int line, c0;
-        seg_of(s, line, c0);
-        if (line < 0) continue;                 // wave-uniform
+        if constexpr (PACK) {
+            line = pk_l0 + s;
+            c0 = pk_c0;
+            if (line >= a.nlines) continue;     // wave-uniform
+        } else {
+            seg_of(s, line, c0);
+            if (line < 0) continue;             // wave-uniform
+        }
         const T *R0 = rec + s * SEG_STRIDE;
         const int k = lane_id_now();
-        const int f = c0 - 1 + k;               // this lane's face
-        bool face_ok = k >= 1 && k <= 62 && f <= a.len;
-        bool cell_ok = k >= 1 && k <= 61 && f < a.len;
+        // this lane's line and position in it (packed: its piece's line and the lane within the piece)
+        int kl = k, lline = line;
+        bool needed = true;                     // the lane's face or its flags are used
+        if constexpr (PACK) {
+            const int i = (k * pk_M) >> 16;
+            kl = k - i * pk_W;
+            lline = pk_l0 + i * NSEG + s;
+            needed = i < pk_P && lline < a.nlines && kl <= pk_nt + 2;
+        }
+        const int f = c0 - 1 + kl;              // this lane's face
+        bool face_ok = needed && kl >= 1 && kl <= 62 && f <= a.len;
+        bool cell_ok = needed && kl >= 1 && kl <= 61 && f < a.len;
         // face index in this direction's face arrays
         auto face_index = [&](int ff) {
             return DIR == 0 ? (size_t)line * (a.len + 1) + ff : (size_t)ff * a.nx + line;
@@ -963,7 +1046,9 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
             } else {
                 Smooth<T> sp = smooth5(vp[1], vp[2], vp[3], vp[4], vp[5]);
                 Smooth<T> sm = smooth5(vm[6], vm[5], vm[4], vm[3], vm[2]);
-                const bool easy = all_smooth(sp, a.eps, a.smooth_k) && all_smooth(sm, a.eps, a.smooth_k);
+                // (lanes of a packed wave that no piece needs count as smooth: their stencils straddle
+                // two lines)
+                const bool easy = (all_smooth(sp, a.eps, a.smooth_k) && all_smooth(sm, a.eps, a.smooth_k)) || !needed;
                 if (__all(easy)) {
                     // every flag of every face of the wave is 1: the full stencil on both sides
                     fword |= 63u << (6 * sf);
@@ -987,8 +1072,8 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
                         mp = table3_rev(ip);
                         mm = table3_rev(im);
                         if (face_ok && (mp == 15 || mm == 15)) bad |= ERR_SELECTION;
-                        mp = mp == 15 ? 0 : mp;
-                        mm = mm == 15 ? 0 : mm;
+                        mp = (mp == 15 || !needed) ? 0 : mp;
+                        mm = (mm == 15 || !needed) ? 0 : mm;
                         mword |= (uint32_t)(mp | (mm << 4)) << (8 * sf);
                     } else {
                         int cp = (int)(((dp & 1u) << 2) | (dp & 2u) | ((dp >> 2) & 1u));
@@ -1025,12 +1110,20 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
         // lane-dependent predicates recomputed from an opaque copy of the lane id (keeping them
         // live across the field loop costs registers the loop needs)
         int fe;                                 // this lane's face again
+        int eline = line;                       // and its line
         {
             int kk = lane_id_now();
             asm volatile("" ::: "memory");      // orders the record reads before the epilogue
+            bool pv = true;
+            if constexpr (PACK) {
+                const int i = (kk * pk_M) >> 16;
+                eline = pk_l0 + i * NSEG + s;
+                pv = i < pk_P && eline < a.nlines;
+                kk -= i * pk_W;
+            }
             fe = c0 - 1 + kk;
-            face_ok = kk >= 1 && kk <= 62 && fe <= a.len;
-            cell_ok = kk >= 1 && kk <= 61 && fe < a.len;
+            face_ok = pv && kk >= 1 && kk <= 62 && fe <= a.len;
+            cell_ok = pv && kk >= 1 && kk <= 61 && fe < a.len;
         }
         if constexpr (MODE == MODE_FACES) {
             if (face_ok) {
@@ -1053,7 +1146,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
             // primitive speeds of the produced cell (stage mode); lanes without a cell contribute 0
             double sx = 0.0, sy = 0.0, sc = 0.0;
             if (cell_ok) {
-                size_t off = DIR == 0 ? (size_t)line * a.nx + fe : (size_t)fe * a.nx + line;
+                size_t off = DIR == 0 ? (size_t)eline * a.nx + fe : (size_t)fe * a.nx + eline;
                 const T *e = ext + (size_t)s * 2 * NV * WAVE + k;
                 T unew[NV];
 #pragma unroll
@@ -1062,7 +1155,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
                     T d = -(Fr[v] - Fh[v]) * a.inv_h;
                     if (a.addend) d = d + (HAS_EXT ? e[(NV + v) * WAVE] : a.addend[go]);
                     if constexpr (STAGE_OUT) {
-                        rec[s * SEG_STRIDE + v * SEG_CELLS + k - 1] = d;   // own record, no longer read
+                        rec[s * SEG_STRIDE + v * OUTW + k - 1] = d;   // own record, no longer read
                     } else if constexpr (MODE == MODE_RHS) {
                         a.out[go] = d;
                     } else {
@@ -1154,7 +1247,17 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
             }
         }
     }
-    if constexpr (STAGE_OUT) {
+    if constexpr (STAGE_OUT && PACK) {
+        __syncthreads();
+        for (int idx = tid; idx < NV * WAVE * NSEG; idx += BLOCK) {
+            const int sg = idx % NSEG, kk = (idx / NSEG) % WAVE, v = idx / (NSEG * WAVE);
+            const int i = ((kk + 1) * pk_M) >> 16, kl = kk + 1 - i * pk_W;   // lane kk + 1
+            const int line = pk_l0 + i * NSEG + sg;
+            if (i >= pk_P || line >= a.nlines || kl < 1 || kl > pk_nt) continue;
+            a.out[(size_t)gvar<SYS, DIR>(v) * ncell + (size_t)(pk_c0 + kl - 1) * a.nx + line] =
+                rec[sg * SEG_STRIDE + v * WAVE + kk];
+        }
+    } else if constexpr (STAGE_OUT) {
         __syncthreads();
         for (int idx = tid; idx < NV * SEG_CELLS * NSEG; idx += BLOCK) {
             const int sg = idx % NSEG, c = (idx / NSEG) % SEG_CELLS, v = idx / (NSEG * SEG_CELLS);

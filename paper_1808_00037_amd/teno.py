@@ -76,6 +76,7 @@ _SIGS = {
     "teno_batch_offset": (ctypes.c_size_t, [_P, ctypes.c_int32]),
     "teno_batch_run": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.c_int32]),
     "teno_batch_poll": (ctypes.c_int, [_P]),
+    "teno_batch_set_shape": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
 }
 
 
@@ -354,6 +355,11 @@ class Batch:
             raise RuntimeError("a Batch runs on the stream it was created on")
         _check(lib().teno_batch_run(self._h, _ptr(buf), int(nsteps), int(mode)), "teno_batch_run")
         return buf
+
+    def set_shape(self, x_tile, y_tile, packed):
+        """Fix mode 0's launch shape (4 or 8 segments per x-tile and columns per y-tile; packed
+        ragged last segments or not) instead of the timing-based choice of the first run."""
+        _check(lib().teno_batch_set_shape(self._h, int(x_tile), int(y_tile), int(packed)), "teno_batch_set_shape")
 
     def poll(self):
         _check(lib().teno_batch_poll(self._h), "batch device status")

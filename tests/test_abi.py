@@ -95,6 +95,7 @@ def test_null_arguments(T):
     assert L.teno_rhs(None, None, None, None) == -1
     assert L.teno_run(None, None, 1, 0.0, 0) == -1
     assert L.teno_batch_destroy(None) == -1
+    assert L.teno_batch_set_shape(None, 4, 4, 1) == -1
 
 
 @pytest.mark.parametrize("bad,code", [(dict(sys=0), -2), (dict(nx=0), -1), (dict(nx=1 << 21), -1),

@@ -18,9 +18,14 @@ pytestmark = pytest.mark.gpu
 
 
 def _problems():
+    # 2D sizes with short ragged last segments (64, 70, 130 along x; 130, 200 along y) are packed
+    # several lines to a wave, over several tail tiles with a partial last one; one instance has
+    # outflow boundaries, where the packed pieces meet the boundary condition
     probs = [W.euler1d(1, n=300), W.euler1d(2, n=1000), W.euler1d(3, n=61), W.euler1d(4, n=4096),
-             W.euler2d(5, n=40), W.euler2d(6, n=64, ny=48), W.euler2d(7, n=33, ny=50), W.euler2d(8, n=130, ny=90)]
+             W.euler2d(5, n=40), W.euler2d(6, n=64, ny=48), W.euler2d(7, n=33, ny=50), W.euler2d(8, n=130, ny=90),
+             W.euler2d(9, n=70, ny=200), W.euler2d(10, n=64, ny=130)]
     probs[2].bc_x = O.PERIODIC
+    probs[9].bc_x = probs[9].bc_y = O.OUTFLOW
     return probs
 
 
@@ -52,6 +57,28 @@ def test_batch_modes_are_bitwise_equal_and_match_single_runs():
     b.run(c, 2, mode=1)
     b.poll()
     assert torch.equal(a, c)
+
+
+def test_every_launch_shape_gives_the_same_states():
+    probs = _problems()
+    b = T.Batch(probs)
+    buf0 = b.pack([torch.from_numpy(p.U0) for p in probs])
+    ref = buf0.clone()
+    b.run(ref, 3, mode=1)
+    b.poll()
+    for xt in (4, 8):
+        for yt in (4, 8):
+            for packed in (0, 1):
+                b.set_shape(xt, yt, packed)
+                a = buf0.clone()
+                b.run(a, 3, mode=0)
+                b.poll()
+                assert torch.equal(a, ref), (xt, yt, packed)
+    with pytest.raises(T.TenoError):
+        b.set_shape(6, 4, 0)
+    with pytest.raises(T.TenoError):
+        b.set_shape(4, 4, 2)
+    b.close()
 
 
 def test_batch_rejects_scalar_systems():
