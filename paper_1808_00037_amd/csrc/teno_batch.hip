@@ -5,15 +5,18 @@
 // block, with the single-problem kernels' tile code and register budget; the list is instance-major
 // and blocks are renumbered per XCD, so blocks running together on one XCD share an instance's rows
 // in L2. Every instance keeps its own Lax-Friedrichs constants, CFL dt and spread wave-speed
-// maxima. Mode 0 captures the whole nsteps run (per step: 3 x [stage prep, y-sweep of the 2D
-// instances, x-sweep + stage update of the 2D and of the 1D instances]) in one HIP graph and
-// launches it once; mode 1 launches the same kernels once per instance per kernel on the stream. A
-// face or cell is computed by the same code whatever tile or launch holds it, and the maxima are
-// exact, so both modes give bitwise identical states.
+// maxima. The short ragged last segments of 2D instances' lines can be left to tail launches whose
+// waves take one such segment of several lines each (a 64-cell line would otherwise fill a second
+// wave with 3 cells). Mode 0 captures the whole nsteps run (per step: 3 x [stage prep, y-sweep of
+// the 2D instances, x-sweep + stage update of the 2D and of the 1D instances]) in one HIP graph and
+// launches it once; mode 1 launches the plain tiles once per instance per kernel on the stream. A
+// face or cell is computed by the same code whatever tile or launch holds it, its multiply-adds are
+// fused as the source writes them, and the maxima are exact, so both modes and every launch shape
+// give bitwise identical states.
 //
-// Tile shapes (segments per x-tile, columns per y-tile) are picked by a small autotuner at the
-// first mode-0 run: each candidate advances a scratch copy of the batch by one step (after a
-// warm-up step) and the fastest is kept for the batch.
+// Launch shapes (segments per x-tile, columns per y-tile, tail packing on or off) are picked by a
+// small autotuner at the first mode-0 run: each candidate advances a scratch copy of the batch by
+// one step (after a warm-up step) and the fastest is kept for the batch.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -245,9 +248,9 @@ struct teno_batch {
     // tuned launch shape
     bool tuned = false;
     int vx = 0, vy = 1, pk = 1;
-    // captured run (a second stream for the parallel branch of the 1D instances)
+    // captured run (a second stream for the parallel branches)
     hipStream_t cap_stream = nullptr, cap_stream2 = nullptr;
-    hipEvent_t ev_fork[3] = {nullptr, nullptr, nullptr}, ev_join[3] = {nullptr, nullptr, nullptr};
+    hipEvent_t ev_fork[2][3] = {}, ev_join[2][3] = {};     // [y phase, x phase][stage]
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     void *graph_U = nullptr;
@@ -313,8 +316,9 @@ Ranges instance_ranges(const teno_batch *b, int k, int vx, int vy)
 }
 
 // Enqueue one SSP-RK3 step of the instances [first, first + count) whose items are r. With a second
-// stream s2 (graph capture), the 1D instances' x-sweep runs on a parallel branch beside the 2D
-// sweeps (it depends on neither) and joins before the next stage.
+// stream s2 (graph capture), the launches that share no data with the main ones run on a parallel
+// branch beside them and join before the next phase: the y tail items beside the y main items, and
+// the x tail items and the 1D instances' x-sweep beside the 2D x main items.
 template <typename T>
 void enqueue_step(teno_batch *b, hipStream_t s, T *U, int first, int count, const Ranges &r, int vx, int vy,
                   hipStream_t s2 = nullptr)
@@ -329,42 +333,55 @@ void enqueue_step(teno_batch *b, hipStream_t s, T *U, int first, int count, cons
         a.stage = k;
         a.U = in[k];
         a.items = b->items_y_d[vy][r.p];
-        a.begin = r.y0;
-        a.end = r.y1;
         a.mode = MODE_RHS;
         a.out = (T *)b->dUy;
+        // y-sweeps
+        const bool fork_y = s2 != nullptr && r.yt1 > r.yt0;
+        BatchSweep<T> at = a;
+        at.begin = r.yt0;
+        at.end = r.yt1;
+        if (fork_y) {
+            (void)hipEventRecord(b->ev_fork[0][k], s);
+            (void)hipStreamWaitEvent(s2, b->ev_fork[0][k], 0);
+            launch_batch_sweep<T, EULER2D, 1, true>(s2, vy, at);
+            (void)hipEventRecord(b->ev_join[0][k], s2);
+        }
+        a.begin = r.y0;
+        a.end = r.y1;
         launch_batch_sweep<T, EULER2D, 1>(s, vy, a);
-        a.begin = r.yt0;
-        a.end = r.yt1;
-        launch_batch_sweep<T, EULER2D, 1, true>(s, vy, a);
+        if (fork_y)
+            (void)hipStreamWaitEvent(s, b->ev_join[0][k], 0);
+        else
+            launch_batch_sweep<T, EULER2D, 1, true>(s, vy, at);
+        // x-sweeps with the stage update
         a.items = b->items_x_d[vx][r.p];
         a.mode = MODE_STAGE;
         a.U0 = U;
         a.addend = (T *)b->dUy;
         a.out = outp[k];
         a.ring_next = (k + 1) % 3;
-        const bool fork = s2 != nullptr && r.x1b > r.x1a;
-        if (fork) {
-            (void)hipEventRecord(b->ev_fork[k], s);
-            (void)hipStreamWaitEvent(s2, b->ev_fork[k], 0);
-            BatchSweep<T> a1 = a;
-            a1.begin = r.x1a;
-            a1.end = r.x1b;
+        BatchSweep<T> a1 = a;
+        a1.begin = r.x1a;
+        a1.end = r.x1b;
+        at = a;
+        at.begin = r.x2ta;
+        at.end = r.x2tb;
+        const bool fork_x = s2 != nullptr && (r.x1b > r.x1a || r.x2tb > r.x2ta);
+        if (fork_x) {
+            (void)hipEventRecord(b->ev_fork[1][k], s);
+            (void)hipStreamWaitEvent(s2, b->ev_fork[1][k], 0);
+            launch_batch_sweep<T, EULER2D, 0, true>(s2, vx, at);
             launch_batch_sweep<T, EULER1D, 0>(s2, vx, a1);
-            (void)hipEventRecord(b->ev_join[k], s2);
+            (void)hipEventRecord(b->ev_join[1][k], s2);
         }
         a.begin = r.x2a;
         a.end = r.x2b;
         launch_batch_sweep<T, EULER2D, 0>(s, vx, a);
-        a.begin = r.x2ta;
-        a.end = r.x2tb;
-        launch_batch_sweep<T, EULER2D, 0, true>(s, vx, a);
-        if (fork) {
-            (void)hipStreamWaitEvent(s, b->ev_join[k], 0);
+        if (fork_x) {
+            (void)hipStreamWaitEvent(s, b->ev_join[1][k], 0);
         } else {
-            a.begin = r.x1a;
-            a.end = r.x1b;
-            launch_batch_sweep<T, EULER1D, 0>(s, vx, a);
+            launch_batch_sweep<T, EULER2D, 0, true>(s, vx, at);
+            launch_batch_sweep<T, EULER1D, 0>(s, vx, a1);
         }
     }
 }
@@ -433,8 +450,10 @@ teno_status run_t(teno_batch *b, T *U, int nsteps, int mode)
         if (!b->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
         if (!b->cap_stream2) HIP_TRY(hipStreamCreateWithFlags(&b->cap_stream2, hipStreamNonBlocking));
         for (int k = 0; k < 3; ++k) {
-            if (!b->ev_fork[k]) HIP_TRY(hipEventCreateWithFlags(&b->ev_fork[k], hipEventDisableTiming));
-            if (!b->ev_join[k]) HIP_TRY(hipEventCreateWithFlags(&b->ev_join[k], hipEventDisableTiming));
+            for (int ph = 0; ph < 2; ++ph) {
+                if (!b->ev_fork[ph][k]) HIP_TRY(hipEventCreateWithFlags(&b->ev_fork[ph][k], hipEventDisableTiming));
+                if (!b->ev_join[ph][k]) HIP_TRY(hipEventCreateWithFlags(&b->ev_join[ph][k], hipEventDisableTiming));
+            }
         }
         HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
         enqueue_init<T>(b, b->cap_stream, U, 0, b->n);
@@ -623,8 +642,10 @@ teno_status teno_batch_destroy(teno_batch *b)
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
     if (b->cap_stream2) (void)hipStreamDestroy(b->cap_stream2);
     for (int k = 0; k < 3; ++k) {
-        if (b->ev_fork[k]) (void)hipEventDestroy(b->ev_fork[k]);
-        if (b->ev_join[k]) (void)hipEventDestroy(b->ev_join[k]);
+        for (int ph = 0; ph < 2; ++ph) {
+            if (b->ev_fork[ph][k]) (void)hipEventDestroy(b->ev_fork[ph][k]);
+            if (b->ev_join[ph][k]) (void)hipEventDestroy(b->ev_join[ph][k]);
+        }
     }
     for (int v = 0; v < 2; ++v)
         for (int p = 0; p < 2; ++p) {
