@@ -138,7 +138,7 @@ __global__ void __launch_bounds__(BLOCK, SYS == EULER1D ? 3 : (DIR == 0 ? TENO_M
     batch_sweep_kernel(BatchSweep<T> b)
 {
     constexpr int MODE = DIR == 0 ? MODE_STAGE : MODE_RHS;
-    __shared__ T rec[NSEG * seg_stride<SYS>()];
+    __shared__ T rec[rec_size<SYS, DIR, NSEG, PACK>()];
     __shared__ __align__(16) T ext[ext_size<T, SYS, DIR, NSEG, MODE>()];
     __shared__ T coef[NCOEF_ROWS * 8];
     __shared__ double red[BLOCK / WAVE * 9];

@@ -748,6 +748,17 @@ __device__ __forceinline__ void block_max_atomic(double w[9], unsigned long long
 // LDS record stride of one staged segment (odd: the y staging stores spread over the banks).
 template <int SYS> constexpr int seg_stride() { return Rec<SYS>::NREC * SEG_LOAD + 1; }
 
+// x-sweeps (other than packed tails) keep one field-major record for the whole tile, [NREC][stride]:
+// the tile's segments, when they lie on one line, overlap at positions 61 s (their cells are staged
+// once), else sit at positions 72 s. Other sweeps keep one record per segment, [NSEG][NREC][72] + 1.
+template <int NSEG> constexpr int xrec_stride() { return NSEG * SEG_LOAD + 1; }
+template <int SYS, int DIR, int NSEG, bool PACK> constexpr int rec_size()
+{
+    return (DIR == 0 && !PACK && Rec<SYS>::NREC * xrec_stride<NSEG>() > NSEG * seg_stride<SYS>())
+               ? Rec<SYS>::NREC * xrec_stride<NSEG>()
+               : NSEG * seg_stride<SYS>();
+}
+
 // Fill the block's coefficient table (rows of Tables 2 and 1, correctly rounded in T).
 template <typename T> __device__ __forceinline__ void fill_coef(T *coef)
 {
@@ -772,6 +783,8 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
     constexpr int NV = Sys<SYS>::NV;
     constexpr int SEG_STRIDE = seg_stride<SYS>();
     constexpr bool EULER = SYS == EULER1D || SYS == EULER2D;
+    constexpr bool XREC = DIR == 0 && !PACK;                 // field-major tile record (x-sweeps)
+    constexpr int FSTR = XREC ? xrec_stride<NSEG>() : SEG_LOAD;   // record stride between fields
 
     const int tid = threadIdx.x, lane = tid & (WAVE - 1), wid = tid / WAVE;
     const size_t ncell = (size_t)a.nx * a.ny;
@@ -813,19 +826,30 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
     const double dtv = MODE == MODE_STAGE ? uniform_f64(*a.dt) : 0.0;
 
     // ---- stage cells into LDS ----
-    // x-sweeps: each wave stages its own segments (runs of SEG_LOAD cells of a row: coalesced, and
-    // the index arithmetic is wave-uniform). y-sweeps: the block stages its NSEG adjacent columns
-    // row by row, so that one global load reads NSEG consecutive doubles of a row. A staged run
-    // spans cells c0-5 .. c0+66 with c0 < len, so for len >= SEG_LOAD one wrap suffices.
+    // x-sweeps: a tile whose segments lie on one line is staged by the whole block in one run of
+    // (NSEG-1) 61 + 72 cells (one pass for 4 segments: the 11-cell overlaps of neighbouring segments
+    // are loaded and converted once); otherwise each wave stages its own segments. y-sweeps: the
+    // block stages its NSEG adjacent columns row by row, so that one global load reads NSEG
+    // consecutive doubles of a row. A staged run spans cells c0-5 .. c0+66 with c0 < len (x tiles:
+    // up to the last segment's), so for len >= SEG_LOAD one wrap suffices.
     unsigned bad = 0;
     const bool near = a.len >= SEG_LOAD;
-    // x-sweeps: a wave stages exactly the segments it computes, so the only block-wide ordering needed
-    // is that of the caller's coefficient table and maxima slots; it is taken here, before any load
-    // is in flight, and each wave then starts on its segment as soon as its own staging is done
-    constexpr bool WAVE_LOCAL = DIR == 0 && TENO_X_WAVE_LOCAL;
+    // packed x tails: a wave stages exactly the segment it computes, so the only block-wide ordering
+    // needed is that of the caller's coefficient table and maxima slots; it is taken here, before any
+    // load is in flight, and each wave then starts as soon as its own staging is done
+    constexpr bool WAVE_LOCAL = DIR == 0 && PACK && TENO_X_WAVE_LOCAL;
     if constexpr (WAVE_LOCAL) lds_barrier();
-    auto stage_cell = [&](int s, int q, size_t off) {
-        T *r = rec + s * SEG_STRIDE + q;
+    // record position of cell q of segment s (the field-major x record: 61 s + q when the tile lies
+    // on one line, else 72 s + q); block-uniform
+    int segoff = SEG_STRIDE;
+    bool xcontig = false;
+    if constexpr (XREC) {
+        const int id0 = tile * NSEG;
+        xcontig = id0 % a.nseg + NSEG <= a.nseg && id0 / a.nseg < a.nlines;
+        segoff = xcontig ? SEG_CELLS : SEG_LOAD;
+    }
+    auto stage_cell = [&](int pos, size_t off) {
+        T *r = rec + pos;
         if constexpr (!EULER) {
             r[0] = a.U[off];
         } else {
@@ -842,13 +866,13 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
             T p = a.gm1 * (E - T(0.5) * rho * (un * un + ut * ut));
             if (!(rho > T(0) && p > T(0))) bad |= (isfinite(rho) && isfinite(p)) ? ERR_NONPHYSICAL : ERR_NONFINITE;
             r[0] = rho;
-            r[SEG_LOAD * 1] = mn;
-            if constexpr (NV == 4) r[SEG_LOAD * 2] = mt;
-            r[SEG_LOAD * S::E] = E;
-            r[SEG_LOAD * S::UN] = un;
-            if constexpr (NV == 4) r[SEG_LOAD * S::UT] = ut;
-            r[SEG_LOAD * S::P] = p;
-            r[SEG_LOAD * S::RS] = rs;
+            r[FSTR * 1] = mn;
+            if constexpr (NV == 4) r[FSTR * 2] = mt;
+            r[FSTR * S::E] = E;
+            r[FSTR * S::UN] = un;
+            if constexpr (NV == 4) r[FSTR * S::UT] = ut;
+            r[FSTR * S::P] = p;
+            r[FSTR * S::RS] = rs;
         }
     };
     // epilogue operands of the owned cells (lanes 1..61), staged with the tile so that their
@@ -864,7 +888,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
                 if (i >= pk_P || line >= a.nlines) line = line0;   // idle positions: any valid cell
                 const int g = near ? bc_index_near(pk_c0 - SEG_HALO + ql, a.len, a.bc)
                                    : bc_index(pk_c0 - SEG_HALO + ql, a.len, a.bc);
-                stage_cell(s, q, (size_t)line * a.nx + g);
+                stage_cell(s * SEG_STRIDE + q, (size_t)line * a.nx + g);
             }
         }
     } else if constexpr (PACK) {
@@ -877,19 +901,37 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
             if (i >= pk_P || line >= a.nlines) line = line0;
             const int g = near ? bc_index_near(pk_c0 - SEG_HALO + ql, a.len, a.bc)
                                : bc_index(pk_c0 - SEG_HALO + ql, a.len, a.bc);
-            stage_cell(s, q, (size_t)g * a.nx + line);
+            stage_cell(s * SEG_STRIDE + q, (size_t)g * a.nx + line);
         }
     } else if constexpr (DIR == 0) {
+        if (xcontig) {
+            constexpr int NCELL = (NSEG - 1) * SEG_CELLS + SEG_LOAD;
+            const int id0 = tile * NSEG;
+            const int c00 = (id0 % a.nseg) * SEG_CELLS;
+            const size_t lbase = (size_t)(id0 / a.nseg) * a.nx;
+            for (int q = tid; q < NCELL; q += BLOCK) {
+                const int g = near ? bc_index_near(c00 - SEG_HALO + q, a.len, a.bc)
+                                   : bc_index(c00 - SEG_HALO + q, a.len, a.bc);
+                stage_cell(q, lbase + g);
+            }
+        } else {
+            for (int s = __builtin_amdgcn_readfirstlane(wid); s < NSEG; s += BLOCK / WAVE) {
+                int line, c0;
+                seg_of(s, line, c0);
+                if (line < 0) continue;         // wave-uniform
+                const size_t lbase = (size_t)line * a.nx;
+                for (int q = lane; q < SEG_LOAD; q += WAVE) {
+                    const int g = near ? bc_index_near(c0 - SEG_HALO + q, a.len, a.bc)
+                                       : bc_index(c0 - SEG_HALO + q, a.len, a.bc);
+                    stage_cell(s * SEG_LOAD + q, lbase + g);
+                }
+            }
+        }
         for (int s = __builtin_amdgcn_readfirstlane(wid); s < NSEG; s += BLOCK / WAVE) {
             int line, c0;
             seg_of(s, line, c0);
             if (line < 0) continue;             // wave-uniform
             const size_t lbase = (size_t)line * a.nx;
-            for (int q = lane; q < SEG_LOAD; q += WAVE) {
-                const int g = near ? bc_index_near(c0 - SEG_HALO + q, a.len, a.bc)
-                                   : bc_index(c0 - SEG_HALO + q, a.len, a.bc);
-                stage_cell(s, q, lbase + g);
-            }
             if constexpr (HAS_EXT) {
                 // the owned cells' U^n and y-part (lanes 1..61 read cells c0 .. c0+60): copied into
                 // LDS in the background (issued after the record loads, which are waited for in
@@ -915,7 +957,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
             if (line >= a.nlines) continue;
             const int g = near ? bc_index_near(c0 - SEG_HALO + q, a.len, a.bc)
                                : bc_index(c0 - SEG_HALO + q, a.len, a.bc);
-            stage_cell(s, q, (size_t)g * a.nx + line);
+            stage_cell(s * SEG_STRIDE + q, (size_t)g * a.nx + line);
         }
     }
     if constexpr (WAVE_LOCAL)
@@ -940,7 +982,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
             seg_of(s, line, c0);
             if (line < 0) continue;             // wave-uniform
         }
-        const T *R0 = rec + s * SEG_STRIDE;
+        const T *R0 = rec + s * segoff;
         const int k = lane_id_now();
         // this lane's line and position in it (packed: its piece's line and the lane within the piece)
         int kl = k, lline = line;
@@ -971,16 +1013,16 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
         if constexpr (EULER) {
             using S = Rec<SYS>;
             const T gm1 = a.gm1;
-            const T rsL = R0[SEG_LOAD * S::RS + k + 3], rsR = R0[SEG_LOAD * S::RS + k + 4];
+            const T rsL = R0[FSTR * S::RS + k + 3], rsR = R0[FSTR * S::RS + k + 4];
             const T sL = R0[k + 3] * rsL, sR = R0[k + 4] * rsR;          // sqrt(rho)
             T isum = recip(sL + sR);
-            roe.un = (sL * R0[SEG_LOAD * S::UN + k + 3] + sR * R0[SEG_LOAD * S::UN + k + 4]) * isum;
+            roe.un = (sL * R0[FSTR * S::UN + k + 3] + sR * R0[FSTR * S::UN + k + 4]) * isum;
             roe.ut = T(0);
             if constexpr (NV == 4)
-                roe.ut = (sL * R0[SEG_LOAD * S::UT + k + 3] + sR * R0[SEG_LOAD * S::UT + k + 4]) * isum;
+                roe.ut = (sL * R0[FSTR * S::UT + k + 3] + sR * R0[FSTR * S::UT + k + 4]) * isum;
             // sqrt(rho) H = (E + p) / sqrt(rho)
-            roe.H = ((R0[SEG_LOAD * S::E + k + 3] + R0[SEG_LOAD * S::P + k + 3]) * rsL +
-                     (R0[SEG_LOAD * S::E + k + 4] + R0[SEG_LOAD * S::P + k + 4]) * rsR) * isum;
+            roe.H = ((R0[FSTR * S::E + k + 3] + R0[FSTR * S::P + k + 3]) * rsL +
+                     (R0[FSTR * S::E + k + 4] + R0[FSTR * S::P + k + 4]) * rsR) * isum;
             roe.q2 = roe.un * roe.un + roe.ut * roe.ut;
             T c2 = gm1 * (roe.H - T(0.5) * roe.q2);
             if (face_ok && !(c2 > T(0))) bad |= isfinite(c2) ? ERR_NONPHYSICAL : ERR_NONFINITE;
@@ -1010,8 +1052,8 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
 #pragma unroll
                 for (int j = 0; j < 8; ++j) {
                     const int q = k + j;
-                    T lu = R0[SEG_LOAD * 2 + q] * Ls[2] + Ls[0] * R0[q];
-                    T lf = R0[SEG_LOAD * Rec<EULER2D>::UN + q] * lu;
+                    T lu = R0[FSTR * 2 + q] * Ls[2] + Ls[0] * R0[q];
+                    T lf = R0[FSTR * Rec<EULER2D>::UN + q] * lu;
                     vp[j] = lf + al * lu;
                     vm[j] = lf - al * lu;
                 }
@@ -1026,10 +1068,10 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
                         lf = SYS == ADV1D ? a.adv * lu : lu * u * T(0.5);
                     } else {
                         using S = Rec<SYS>;
-                        T un = R0[SEG_LOAD * S::UN + q], p = R0[SEG_LOAD * S::P + q];
+                        T un = R0[FSTR * S::UN + q], p = R0[FSTR * S::P + q];
                         lu = Ls[0] * R0[q];
 #pragma unroll
-                        for (int v = 1; v < NV; ++v) lu += Ls[v] * R0[SEG_LOAD * v + q];
+                        for (int v = 1; v < NV; ++v) lu += Ls[v] * R0[FSTR * v + q];
                         // L_s F = u_n (L_s U) + p (L_s[n] + u_n L_s[E]): F = u_n U + p (0, 1, 0, u_n)
                         lf = un * lu + p * (Ls[1] + un * Ls[NV - 1]);
                     }
@@ -1160,7 +1202,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
                         a.out[go] = d;
                     } else {
                         // SSP-RK3 stage, Shu-Osher form
-                        T uk = R0[SEG_LOAD * v + k + 4];   // staged record: conserved variable v first
+                        T uk = R0[FSTR * v + k + 4];   // staged record: conserved variable v first
                         // U^n: the staged stage input itself at the first stage, else its copy
                         T u0 = HAS_EXT ? (a.U0 == a.U ? uk : e[v * WAVE]) : a.U0[go];
                         T dt = (T)dtv;
@@ -1183,13 +1225,16 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
                 // this segment's maxima into the wave's LDS slots (the wave owns them: no race)
                 constexpr int NU = SpeedWords<NV>::count();
                 constexpr int WSTRIDE = WAVE + 1;          // per word, padded against bank conflicts
-                if constexpr (sizeof(T) == 8 && NU * WSTRIDE <= SEG_STRIDE) {
+                constexpr int SWROOM = XREC ? 2 * NV * WAVE - 1 : SEG_STRIDE;
+                if constexpr (sizeof(T) == 8 && NU * WSTRIDE <= SWROOM) {
                     // Through the segment's own record, which is no longer read: every lane stores its
                     // words, then lane 8u+j takes the maximum of values j, j+8, .., j+56 of word slot u
                     // and three row shifts bring the slot's maximum to lane 8u+7. Exact (a maximum of
                     // doubles), and far fewer instructions than a whole-wave reduction per word.
-                    T *sw = rec + s * SEG_STRIDE;
-                    asm volatile("" ::: "memory");     // after the epilogue's record reads
+                    // (x-stage: the segment's epilogue-operand slot instead, past its element 0, which
+                    // the previous segment's copy may still be writing; the tile record is shared)
+                    T *sw = XREC ? ext + (size_t)s * 2 * NV * WAVE + 1 : rec + s * SEG_STRIDE;
+                    asm volatile("" ::: "memory");     // after the epilogue's reads
                     {
                         int u = 0;
 #pragma unroll
@@ -1318,7 +1363,7 @@ __global__ void __launch_bounds__(BLOCK, SYS == EULER1D ? 3 : (DIR == 0 ? TENO_M
         a.flags_out = nullptr;
     }
     constexpr int NSEG = DIR == 0 ? NSEG_X : NSEG_Y;
-    __shared__ T rec[NSEG * seg_stride<SYS>()];
+    __shared__ T rec[rec_size<SYS, DIR, NSEG, false>()];
     __shared__ __align__(16) T ext[ext_size<T, SYS, DIR, NSEG, MODE>()];
     __shared__ T coef[NCOEF_ROWS * 8];
     __shared__ double red[BLOCK / WAVE * 9];
