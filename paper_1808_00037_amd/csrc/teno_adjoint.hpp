@@ -85,15 +85,17 @@ __global__ void __launch_bounds__(BLOCK) vjp_kernel(VjpArgs a)
         coef[q] = l < 7 ? (double)COEF[r][l].n / (double)COEF[r][l].d : 0.0;
     }
 
+    // tiles renumbered per XCD (neighbouring tiles share cache lines of the staged rows in one L2)
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
     auto seg_of = [&](int s, int &line, int &c0) {
         if (DIR == 0) {
-            int id = blockIdx.x * ADJ_NSEG + s;
+            int id = tile * ADJ_NSEG + s;
             line = id / a.nseg;
             c0 = (id % a.nseg) * ADJ_CELLS;
         } else {
             int ntile = (a.nlines + ADJ_NSEG - 1) / ADJ_NSEG;
-            line = (blockIdx.x % ntile) * ADJ_NSEG + s;
-            c0 = (blockIdx.x / ntile) * ADJ_CELLS;
+            line = (tile % ntile) * ADJ_NSEG + s;
+            c0 = (tile / ntile) * ADJ_CELLS;
         }
         if (line >= a.nlines) line = -1;
     };
@@ -119,7 +121,10 @@ __global__ void __launch_bounds__(BLOCK) vjp_kernel(VjpArgs a)
             double mn = a.U[(size_t)gvar<SYS, DIR>(1) * ncell + off];
             double mt = NV == 4 ? a.U[(size_t)gvar<SYS, DIR>(2) * ncell + off] : 0.0;
             double E = a.U[(size_t)(NV - 1) * ncell + off];
-            double ir = 1.0 / rho;
+            double sq, rs;
+            sqrt_rsqrt(rho, sq, rs);
+            double ir = rs * rs;
+            if (!(rho > 0.0)) ir = 1.0 / rho;
             double un = mn * ir, ut = mt * ir;
             double p = (a.gamma - 1.0) * (E - 0.5 * rho * (un * un + ut * ut));
             r[0] = rho;
@@ -129,7 +134,7 @@ __global__ void __launch_bounds__(BLOCK) vjp_kernel(VjpArgs a)
             r[SEG_LOAD * S::UN] = un;
             if constexpr (NV == 4) r[SEG_LOAD * S::UT] = ut;
             r[SEG_LOAD * S::P] = p;
-            r[SEG_LOAD * S::S] = sqrt(rho);
+            r[SEG_LOAD * S::RS] = rs;                            // 1/sqrt(rho)
             r[SEG_LOAD * S::H] = (E + p) * ir;
         }
 #pragma unroll
@@ -171,16 +176,16 @@ __global__ void __launch_bounds__(BLOCK) vjp_kernel(VjpArgs a)
         double W = 1.0, iW = 1.0;
         if constexpr (EULER) {
             using S = Sys<SYS>;
-            double sL = R0[SEG_LOAD * S::S + k + 3], sR = R0[SEG_LOAD * S::S + k + 4];
+            // sqrt(rho) = rho / sqrt(rho) from the staged reciprocal square root
+            double sL = R0[k + 3] * R0[SEG_LOAD * S::RS + k + 3], sR = R0[k + 4] * R0[SEG_LOAD * S::RS + k + 4];
             W = sL + sR;
-            iW = 1.0 / W;
+            iW = recip(W);
             roe.un = (sL * R0[SEG_LOAD * S::UN + k + 3] + sR * R0[SEG_LOAD * S::UN + k + 4]) * iW;
             if constexpr (NV == 4) roe.ut = (sL * R0[SEG_LOAD * S::UT + k + 3] + sR * R0[SEG_LOAD * S::UT + k + 4]) * iW;
             roe.H = (sL * R0[SEG_LOAD * S::H + k + 3] + sR * R0[SEG_LOAD * S::H + k + 4]) * iW;
             roe.q2 = roe.un * roe.un + roe.ut * roe.ut;
             double c2 = gm1 * (roe.H - 0.5 * roe.q2);
-            roe.cs = sqrt(c2 > 0.0 ? c2 : 1.0);
-            roe.ic = 1.0 / roe.cs;
+            sqrt_rsqrt(c2 > 0.0 ? c2 : 1.0, roe.cs, roe.ic);
             roe.b1 = gm1 * roe.ic * roe.ic;
             roe.b2 = 0.5 * roe.b1 * roe.q2;
         }
@@ -320,18 +325,18 @@ __global__ void __launch_bounds__(BLOCK) vjp_kernel(VjpArgs a)
 #pragma unroll
             for (int side = 0; side < 2; ++side) {
                 const int q = k + 3 + side;
-                const double rho = R0[q], sq = R0[SEG_LOAD * S::S + q];
+                const double rho = R0[q], rsq = R0[SEG_LOAD * S::RS + q], sq = rho * rsq;
                 const double uc = R0[SEG_LOAD * S::UN + q];
                 const double vc = NV == 4 ? R0[SEG_LOAD * S::UT + q] : 0.0;
                 const double Hc = R0[SEG_LOAD * S::H + q];
                 double sb = (unb * (uc - un) + utb * (vc - ut) + Hb * (Hc - roe.H)) * iW;
                 double ucb = unb * sq * iW, vcb = utb * sq * iW, Hcb = Hb * sq * iW;
-                const double ir = 1.0 / rho;
+                const double ir = rsq * rsq;
                 double g[NV];
 #pragma unroll
                 for (int v = 0; v < NV; ++v) g[v] = 0.0;
                 // sqrt(rho)
-                g[0] += sb * 0.5 / sq;
+                g[0] += sb * 0.5 * rsq;
                 // u = m_n / rho, v = m_t / rho
                 g[1] += ucb * ir;
                 g[0] += -ucb * uc * ir;

@@ -89,17 +89,17 @@ struct Ctrl {
 
 // ------------------------------------------------------------------------------------------------
 // System traits: number of conserved variables, staged record layout.
-// Euler records hold (rho, m_n, [m_t], E, u_n, [u_t], p, sqrt(rho), H), with n the sweep direction;
+// Adjoint Euler records hold (rho, m_n, [m_t], E, u_n, [u_t], p, 1/sqrt(rho), H), n the sweep direction;
 // the conserved variables come first, so record index v is local conserved variable v.
 // ------------------------------------------------------------------------------------------------
 template <int SYS> struct Sys;
 template <> struct Sys<ADV1D> { static constexpr int NV = 1, NREC = 1; };
 template <> struct Sys<BURGERS1D> { static constexpr int NV = 1, NREC = 1; };
 template <> struct Sys<EULER1D> {
-    static constexpr int NV = 3, NREC = 7, E = 2, UN = 3, UT = -1, P = 4, S = 5, H = 6;
+    static constexpr int NV = 3, NREC = 7, E = 2, UN = 3, UT = -1, P = 4, RS = 5, H = 6;
 };
 template <> struct Sys<EULER2D> {
-    static constexpr int NV = 4, NREC = 9, E = 3, UN = 4, UT = 5, P = 6, S = 7, H = 8;
+    static constexpr int NV = 4, NREC = 9, E = 3, UN = 4, UT = 5, P = 6, RS = 7, H = 8;
 };
 
 // Staged per-cell record of the forward sweeps: the conserved variables in local order, then u_n,
