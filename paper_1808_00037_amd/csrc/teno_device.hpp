@@ -748,6 +748,17 @@ __device__ __forceinline__ void block_max_atomic(double w[9], unsigned long long
 // LDS record stride of one staged segment (odd: the y staging stores spread over the banks).
 template <int SYS> constexpr int seg_stride() { return Rec<SYS>::NREC * SEG_LOAD + 1; }
 
+// LDS pointer type, and the record field of the projection's i-th stencil operand (the conserved
+// variables, then u_n and p).
+template <typename T> using lds_cptr = __attribute__((address_space(3))) const T *;
+template <int SYS> constexpr int proj_field(int i)
+{
+    if constexpr (SYS == EULER1D || SYS == EULER2D)
+        return i < Sys<SYS>::NV ? i : (i == Sys<SYS>::NV ? Rec<SYS>::UN : Rec<SYS>::P);
+    else
+        return 0;
+}
+
 // x-sweeps (other than packed tails) keep one field-major record for the whole tile, [NREC][stride]:
 // the tile's segments, when they lie on one line, overlap at positions 61 s (their cells are staged
 // once), else sit at positions 72 s. Other sweeps keep one record per segment, [NSEG][NREC][72] + 1.
@@ -1031,6 +1042,18 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
             roe.b2 = T(0.5) * roe.b1 * roe.q2;
         }
 
+        // LDS addresses of this lane's stencil in the record fields the projection reads (the
+        // conserved variables, u_n, p), made opaque so that they stay in registers across the field
+        // loop: the fields lie farther apart than the paired reads' offsets reach, and addresses
+        // rebuilt from the lane's base would cost an add per paired read
+        constexpr int NPF = EULER ? NV + 2 : 1;
+        lds_cptr<T> Fp[NPF];
+#pragma unroll
+        for (int i = 0; i < NPF; ++i) {
+            Fp[i] = (lds_cptr<T>)(R0 + FSTR * proj_field<SYS>(i) + k);
+            asm volatile("" : "+v"(Fp[i]));
+        }
+
         // Characteristic fields one at a time (kept as a loop: only one field's split values are
         // live, which keeps the wave's register budget low enough for several waves per SIMD).
 #pragma unroll 1
@@ -1051,27 +1074,24 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
                 // shear field: L_2 = (-u_t, 0, 1, 0), so L_2 U = m_t - u_t rho and L_2 F = u_n L_2 U
 #pragma unroll
                 for (int j = 0; j < 8; ++j) {
-                    const int q = k + j;
-                    T lu = R0[FSTR * 2 + q] * Ls[2] + Ls[0] * R0[q];
-                    T lf = R0[FSTR * Rec<EULER2D>::UN + q] * lu;
+                    T lu = Fp[2][j] * Ls[2] + Ls[0] * Fp[0][j];
+                    T lf = Fp[NV][j] * lu;                    // u_n
                     vp[j] = lf + al * lu;
                     vm[j] = lf - al * lu;
                 }
             } else {
 #pragma unroll
                 for (int j = 0; j < 8; ++j) {
-                    const int q = k + j;
                     T lu, lf;
                     if constexpr (!EULER) {
-                        T u = R0[q];
+                        T u = Fp[0][j];
                         lu = T(0.5) * u;
                         lf = SYS == ADV1D ? a.adv * lu : lu * u * T(0.5);
                     } else {
-                        using S = Rec<SYS>;
-                        T un = R0[FSTR * S::UN + q], p = R0[FSTR * S::P + q];
-                        lu = Ls[0] * R0[q];
+                        T un = Fp[NV][j], p = Fp[NV + 1][j];
+                        lu = Ls[0] * Fp[0][j];
 #pragma unroll
-                        for (int v = 1; v < NV; ++v) lu += Ls[v] * R0[FSTR * v + q];
+                        for (int v = 1; v < NV; ++v) lu += Ls[v] * Fp[v][j];
                         // L_s F = u_n (L_s U) + p (L_s[n] + u_n L_s[E]): F = u_n U + p (0, 1, 0, u_n)
                         lf = un * lu + p * (Ls[1] + un * Ls[NV - 1]);
                     }
