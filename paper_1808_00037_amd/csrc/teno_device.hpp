@@ -540,6 +540,20 @@ template <int CTRL> __device__ __forceinline__ float dpp_shift(float v)
 template <int CTRL> __device__ __forceinline__ unsigned dpp_shift(unsigned v) { return dpp_word<CTRL>(v); }
 template <typename T> __device__ __forceinline__ T shfl_up1(T v) { return dpp_shift<0x138>(v); }
 template <typename T> __device__ __forceinline__ T shfl_dn1(T v) { return dpp_shift<0x130>(v); }
+// Same moves for a double where lanes without a source may read 0 (bound_ctrl): one instruction per
+// word, no copy of the old value.
+template <int CTRL> __device__ __forceinline__ double dpp_shift_z(double v)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xf, 0xf, true);
+    const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xf, 0xf, true);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+template <int CTRL> __device__ __forceinline__ float dpp_shift_z(float v)
+{
+    return __uint_as_float((unsigned)__builtin_amdgcn_update_dpp(0, (int)__float_as_uint(v), CTRL, 0xf, 0xf, true));
+}
+template <typename T> __device__ __forceinline__ T shfl_dn1_z(T v) { return dpp_shift_z<0x130>(v); }
 
 // ------------------------------------------------------------------------------------------------
 // Sweep kernel arguments.
@@ -1110,7 +1124,8 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
                 Smooth<T> sm = smooth5(vm[6], vm[5], vm[4], vm[3], vm[2]);
                 // (lanes of a packed wave that no piece needs count as smooth: their stencils straddle
                 // two lines)
-                const bool easy = (all_smooth(sp, a.eps, a.smooth_k) && all_smooth(sm, a.eps, a.smooth_k)) || !needed;
+                // (both sides evaluated, without a branch between them)
+                const bool easy = (all_smooth(sp, a.eps, a.smooth_k) & all_smooth(sm, a.eps, a.smooth_k)) | !needed;
                 if (__all(easy)) {
                     // every flag of every face of the wave is 1: the full stencil on both sides
                     fword |= 63u << (6 * sf);
@@ -1204,7 +1219,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
             if constexpr (HAS_EXT) wait_vmem();  // the background copies of the epilogue operands
             T Fr[NV];
 #pragma unroll
-            for (int v = 0; v < NV; ++v) Fr[v] = shfl_dn1(Fh[v]);
+            for (int v = 0; v < NV; ++v) Fr[v] = shfl_dn1_z(Fh[v]);   // (lane 63, never a cell: 0)
             // primitive speeds of the produced cell (stage mode); lanes without a cell contribute 0
             double sx = 0.0, sy = 0.0, sc = 0.0;
             if (cell_ok) {
@@ -1260,9 +1275,9 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
 #pragma unroll
                         for (int q = 0; q < 9; ++q) {
                             if (!SpeedWords<NV>::use(q)) continue;
-                            sw[u * WSTRIDE + k] = cell_ok ? speed_word<SYS>(q, sx, sy, sc, (double)a.inv_dx,
-                                                                            (double)a.inv_dy, a.alpha_mode)
-                                                          : 0.0;
+                            // (lanes without a cell have zero speeds, so all their words are 0)
+                            sw[u * WSTRIDE + k] = speed_word<SYS>(q, sx, sy, sc, (double)a.inv_dx, (double)a.inv_dy,
+                                                                  a.alpha_mode);
                             ++u;
                         }
                     }
@@ -1273,9 +1288,9 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
 #pragma unroll
                         for (int i = 0; i < 8; ++i) m = fmax(m, (double)sw[u * WSTRIDE + j + 8 * i]);
                     }
-                    m = fmax(m, dpp_shift<0x111>(m));  // row_shr:1
-                    m = fmax(m, dpp_shift<0x112>(m));  // row_shr:2
-                    m = fmax(m, dpp_shift<0x114>(m));  // row_shr:4
+                    m = fmax(m, dpp_shift_z<0x111>(m));  // row_shr:1 (lanes without a source: 0)
+                    m = fmax(m, dpp_shift_z<0x112>(m));  // row_shr:2
+                    m = fmax(m, dpp_shift_z<0x114>(m));  // row_shr:4
                     if (j == 7 && u < NU) {
                         const int q = (int)((SpeedWords<NV>::pack() >> (4 * u)) & 15u);   // word of slot u
                         red[wid * 9 + q] = fmax(red[wid * 9 + q], m);
@@ -1287,8 +1302,8 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
 #pragma unroll
                     for (int q = 0; q < 9; ++q) {
                         if (!SpeedWords<NV>::use(q)) continue;
-                        const double val = cell_ok ? speed_word<SYS>(q, sx, sy, sc, (double)a.inv_dx, (double)a.inv_dy,
-                                                                     a.alpha_mode) : 0.0;
+                        const double val = speed_word<SYS>(q, sx, sy, sc, (double)a.inv_dx, (double)a.inv_dy,
+                                                           a.alpha_mode);
                         const unsigned long long b = (unsigned long long)__double_as_longlong(val);
                         hi[q] = (unsigned)(b >> 32);
                         lo[q] = (unsigned)b;
