@@ -1338,14 +1338,31 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
                 rec[sg * SEG_STRIDE + v * WAVE + kk];
         }
     } else if constexpr (STAGE_OUT) {
+        // thread t stores column t mod NSEG of the tile, entries (v, c) = t / NSEG, t / NSEG + BLOCK /
+        // NSEG, .. of the flattened [NV][SEG_CELLS] results, the pair advanced without divisions
+        static_assert(BLOCK % NSEG == 0, "a fixed column per thread");
+        constexpr int STEP = BLOCK / NSEG, DV = STEP / SEG_CELLS, DC = STEP % SEG_CELLS;
         __syncthreads();
-        for (int idx = tid; idx < NV * SEG_CELLS * NSEG; idx += BLOCK) {
-            const int sg = idx % NSEG, c = (idx / NSEG) % SEG_CELLS, v = idx / (NSEG * SEG_CELLS);
-            int line, c0;
-            seg_of(sg, line, c0);
-            if (line < 0 || c0 + c >= a.len) continue;
-            a.out[(size_t)gvar<SYS, DIR>(v) * ncell + (size_t)(c0 + c) * a.nx + line] =
-                rec[sg * SEG_STRIDE + v * SEG_CELLS + c];
+        const int sg = tid % NSEG;
+        int line, c0;
+        seg_of(sg, line, c0);
+        if (line >= 0) {
+            const T *src = rec + sg * SEG_STRIDE;
+            int v = 0, c = tid / NSEG;              // (tid / NSEG < SEG_CELLS for NSEG >= 8; else wrap)
+            if (c >= SEG_CELLS) {
+                c -= SEG_CELLS;
+                ++v;
+            }
+            for (int it = tid / NSEG; it < NV * SEG_CELLS; it += STEP) {
+                if (c0 + c < a.len)
+                    a.out[(size_t)gvar<SYS, DIR>(v) * ncell + (size_t)(c0 + c) * a.nx + line] = src[v * SEG_CELLS + c];
+                v += DV;
+                c += DC;
+                if (c >= SEG_CELLS) {
+                    c -= SEG_CELLS;
+                    ++v;
+                }
+            }
         }
     }
     if (bad) atomicOr(a.err, bad);
