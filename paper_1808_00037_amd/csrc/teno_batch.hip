@@ -134,7 +134,7 @@ __device__ __forceinline__ SweepArgs<T> item_args(const BatchSweep<T> &b, const 
 // instance's next ring slot. The grid is exactly the item range [begin, end).
 // PACK: tail items, each the ragged last segments of NSEG x P lines of one instance (P per wave).
 template <typename T, int SYS, int DIR, int NSEG, bool PACK>
-__global__ void __launch_bounds__(BLOCK, SYS == EULER1D ? 3 : (DIR == 0 ? TENO_MIN_WAVES_X : TENO_MIN_WAVES_Y))
+__global__ void __launch_bounds__(BLOCK, DIR == 0 ? TENO_MIN_WAVES_X : TENO_MIN_WAVES_Y)
     batch_sweep_kernel(BatchSweep<T> b)
 {
     constexpr int MODE = DIR == 0 ? MODE_STAGE : MODE_RHS;

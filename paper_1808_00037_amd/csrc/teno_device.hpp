@@ -750,8 +750,8 @@ __device__ __forceinline__ void block_max_atomic(double w[9], unsigned long long
 //   FROZEN: the selection is read from masks_in instead of being measured.
 // ------------------------------------------------------------------------------------------------
 // Register budget of the sweep kernels: the minimum number of waves per SIMD the compiler must fit.
-// Measured on MI355X (2D Euler, FP64, 4096^2): 4 for x-sweeps, 3 for y-sweeps (whose 8-column LDS
-// tile admits at most three blocks per CU); 1D Euler sweeps keep 3 (4 makes them spill).
+// Measured on MI355X (2D Euler, FP64, 4096^2): 4 for x- and y-sweeps; frozen-selection 1D Euler
+// sweeps keep 3 (4 makes them spill).
 #ifndef TENO_MIN_WAVES_X
 #define TENO_MIN_WAVES_X 4
 #endif
@@ -1407,7 +1407,7 @@ template <typename T, int SYS, int DIR, int NSEG, int MODE> constexpr int ext_si
 // REC = false: no selection masks or flags are written (the pointers are known null at compile
 // time, so the mask words are not assembled at all).
 template <typename T, int SYS, int DIR, bool FROZEN, int MODE, bool REC = true>
-__global__ void __launch_bounds__(BLOCK, SYS == EULER1D ? 3 : (DIR == 0 ? TENO_MIN_WAVES_X : TENO_MIN_WAVES_Y))
+__global__ void __launch_bounds__(BLOCK, (SYS == EULER1D && FROZEN) ? 3 : (DIR == 0 ? TENO_MIN_WAVES_X : TENO_MIN_WAVES_Y))
     sweep_kernel(SweepArgs<T> a)
 {
     if constexpr (!REC) {
