@@ -76,6 +76,29 @@ def measured_traffic():
         return None
 
 
+def measured_peaks():
+    """Peaks measured on this device beside the published ones: a plain device-to-device copy of
+    1 GiB (read + write bytes over its time, best of 5) and the library's FP64 vector FMA probe."""
+    import torch
+    from paper_1808_00037_amd import teno as T
+
+    src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    best = float("inf")
+    for _ in range(5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    copy_gbps = 2 * src.numel() * 8 / (best / 1e3) / 1e9
+    del src, dst
+    fma = max(T.probe_fp64_fma(32768) for _ in range(3))
+    return {"copy_GBps": copy_gbps, "fp64_fma_TFLOPs": fma}
+
+
 def cpu_baseline(problem, budget_s=12.0):
     """The oracle (plain C, one thread) on a bounded sample of the same workload: one operator
     evaluation on a horizontal strip of the 4096^2 state (periodic), the strip height chosen so
@@ -187,9 +210,24 @@ def adjoint_cost(n=1024, nsteps=400, ckpt=20, seed=21):
         fd = float((Jp - Jm) / (2 * h))
         an = float(torch.sum(lam * d))
         worst = max(worst, abs(fd - an) / abs(an))
+    # the unfrozen map in the first direction: each perturbed run measures its own selection; report
+    # its central difference and the mask words that differ from the base run's
+    d = torch.from_numpy(W.random_directions(77, pr.U0, 1)[0]).cuda()
+    h = 1e-6 * U0.abs().max() / d.abs().max()
+    Js, flips = [], 0
+    for sgn in (1.0, -1.0):
+        Uq = U0 + sgn * h * d
+        rq = sv.run_record(Uq, nsteps, ckpt)
+        Js.append(torch.sqrt(torch.sum((Uq[0] - target) ** 2) * area))
+        flips += int((rq["masks"] != rec["masks"]).sum())
+        del rq
     sv.poll()
+    an = float(torch.sum(lam * d))
+    fd_unfrozen = float((Js[0] - Js[1]) / (2 * h))
     return {"n": n, "steps": nsteps, "ckpt_every": ckpt, "ms_forward": t_fwd, "ms_record": t_rec,
-            "ms_backward": t_bwd, "bwd_over_fwd": t_bwd / t_fwd, "fd_rel_err_2dirs": worst}
+            "ms_backward": t_bwd, "bwd_over_fwd": t_bwd / t_fwd, "fwd_plus_bwd_over_fwd": (t_fwd + t_bwd) / t_fwd,
+            "fd_rel_err_2dirs": worst, "unfrozen_fd_rel_err": abs(fd_unfrozen - an) / abs(an),
+            "unfrozen_mask_flips": flips, "mask_words_per_run": int(rec["masks"].numel())}
 
 
 def scheme_cost(n=4096, steps=10, seed=1):
@@ -326,10 +364,13 @@ def main():
         f"eager step {ms_eager / args.steps:.3f} ms")
     flops_x = FLOPS_XSTAGE * cells
     achieved = flops_x / (x_ms / 1e3)
+    log("measured peaks (copy, FP64 FMA)")
+    peaks = measured_peaks()
     roofline = {"bound": "alu", "kernel": "sweep_kernel<double,EULER2D,x,stage>", "achieved": achieved / 1e12,
                 "peak": PEAK_FP64_VALU / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU,
                 "traffic": measured_traffic(), "avg_launch_ms": x_ms,
-                "flops_per_cell": FLOPS_XSTAGE}
+                "flops_per_cell": FLOPS_XSTAGE, "measured_peak": peaks["fp64_fma_TFLOPs"],
+                "frac_of_measured": achieved / 1e12 / peaks["fp64_fma_TFLOPs"]}
     hbm_frac = value * 1e9 * BYTES_PER_CELL_UPDATE / PEAK_HBM
 
     out = {"metric": METRIC, "value": value, "unit": "Gcell-updates/s", "n_gpus": 1, "steps": args.steps,
@@ -340,6 +381,8 @@ def main():
            "roofline": roofline,
            "hbm": {"algorithmic_bytes_per_cell_update": BYTES_PER_CELL_UPDATE,
                    "achieved_GBps": value * BYTES_PER_CELL_UPDATE, "peak_GBps": PEAK_HBM / 1e9, "frac": hbm_frac,
+                   "copy_GBps": peaks["copy_GBps"],
+                   "frac_of_copy": value * BYTES_PER_CELL_UPDATE / peaks["copy_GBps"],
                    # the x-stage kernel's HBM bytes per launch measured by rocprofv3 (FETCH_SIZE +
                    # WRITE_SIZE, calibrated) over its live launch time
                    "x_stage_measured_GBps": (roofline["traffic"] / (x_ms / 1e3) / 1e9

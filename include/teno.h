@@ -81,6 +81,12 @@ void teno_default_opts(teno_opts *o);
 /* Human-readable name of a status code (static string). */
 const char *teno_status_str(teno_status s);
 
+/* Measurement support (not part of the method): the current device's FP64 vector FMA rate in
+ * TFLOP/s (an FMA counted as 2 flops), from a register-resident FMA loop of `iters` steps per chain
+ * run over every compute unit on `stream` and timed with HIP events. Blocking; allocates and frees
+ * a small output buffer. Errors: TENO_E_ARG (null tflops, iters outside 1..2^24), TENO_E_HIP. */
+teno_status teno_probe_fp64_fma(void *stream, int32_t iters, double *tflops);
+
 /* Create a context for one problem on the current HIP device; `stream` is a hipStream_t (NULL =
  * the null stream). Allocates the context's own device scratch: three state-sized buffers for the
  * RK3 stages and a small control block. Errors: TENO_E_ARG for an invalid grid/opts,

@@ -77,6 +77,7 @@ _SIGS = {
     "teno_batch_run": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.c_int32]),
     "teno_batch_poll": (ctypes.c_int, [_P]),
     "teno_batch_set_shape": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    "teno_probe_fp64_fma": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]),
 }
 
 
@@ -316,6 +317,13 @@ def rhs(U, solver):
 
 def trajectory(U0, solver, nsteps, ckpt_every=20, dt=0.0):
     return TenoTrajectory.apply(U0, solver, nsteps, ckpt_every, dt)
+
+
+def probe_fp64_fma(iters=4096):
+    """Measured FP64 vector FMA rate of the current device, TFLOP/s (an FMA counted as 2 flops)."""
+    out = ctypes.c_double(0.0)
+    _check(lib().teno_probe_fp64_fma(_stream(), int(iters), ctypes.byref(out)), "teno_probe_fp64_fma")
+    return out.value
 
 
 class Batch:
