@@ -93,6 +93,54 @@ def advection_exact(problem, t):
 
 
 # ------------------------------------------------------------------------------------------------
+# The paper's own linear-advection data (section "Linear advection"): u1, a Gaussian on [0, 1); u2 =
+# sin(pi x)^3 on [0, 2); u3, the four-wave profile on [-1, 1). As printed, u3's pieces lie on
+# [0.2, 1.6], partly outside the domain and away from their own centres; they are taken 1 to the left
+# ([-0.8, -0.6] around z = -0.7, [-0.4, -0.2], [0, 0.2], [0.4, 0.6]), which puts each stated centre
+# (z, 0.1, a = 0.5) inside its piece.
+# ------------------------------------------------------------------------------------------------
+_U3_DELTA = 0.005
+_U3_ALPHA = 10.0
+_U3_BETA = math.log(2.0) / (36.0 * _U3_DELTA * _U3_DELTA)
+
+
+def _u3(x):
+    d, al, be = _U3_DELTA, _U3_ALPHA, _U3_BETA
+    z, a = -0.7, 0.5
+    g = lambda c: np.exp(-be * (x - c) ** 2)
+    f = lambda c: np.sqrt(np.maximum(1.0 - al * al * (x - c) ** 2, 0.0))
+    u = np.zeros_like(x)
+    m = (x >= -0.8) & (x <= -0.6)
+    u[m] = ((g(z - d) + g(z + d) + 4.0 * g(z)) / 6.0)[m]
+    u[(x >= -0.4) & (x <= -0.2)] = 1.0
+    m = (x >= 0.0) & (x <= 0.2)
+    u[m] = (1.0 - np.abs(10.0 * (x - 0.1)))[m]
+    m = (x >= 0.4) & (x <= 0.6)
+    u[m] = ((f(a - d) + f(a + d) + 4.0 * f(a)) / 6.0)[m]
+    return u
+
+
+PAPER_ADVECTION = {
+    "u1": (0.0, 1.0, lambda x: np.exp(-300.0 * (x - 0.5) ** 2)),
+    "u2": (0.0, 2.0, lambda x: np.sin(np.pi * x) ** 3),
+    "u3": (-1.0, 1.0, _u3),
+}
+
+
+def paper_advection(kind, n, cfl=0.2, periods=1):
+    """u_t + u_x = 0, periodic, with the paper's initial data `kind`, run for whole periods at a fixed
+    dt = cfl dx (the exact solution is then the initial data)."""
+    x0, x1, fn = PAPER_ADVECTION[kind]
+    x = cell_centres(x0, x1, n)
+    U0 = fn(x)[None, None, :].astype(np.float64)
+    dx = (x1 - x0) / n
+    dt = cfl * dx
+    nsteps = int(round(periods * (x1 - x0) / dt))
+    return Problem(f"advection_{kind}", ADV1D, n, 1, x0, x1, 0.0, 1.0, PERIODIC, PERIODIC, U0,
+                   cfl=cfl, dt=dt, nsteps=nsteps, meta=dict(t_end=nsteps * dt))
+
+
+# ------------------------------------------------------------------------------------------------
 # Inviscid Burgers: u_t + (u^2/2)_x = 0 on [0, 2), periodic, u0 = 1/2 + sin(pi (x - shift)) (the
 # paper's case at shift = 0; smooth until t = 1/pi, then a shock forms).
 # ------------------------------------------------------------------------------------------------
@@ -230,7 +278,8 @@ def random_directions(seed, U0, count):
 
 
 # ------------------------------------------------------------------------------------------------
-# The paper's one-dimensional shock tubes (section "Isolated wave structure") and Shu-Osher.
+# The paper's one-dimensional shock tubes (section "Isolated wave structure") and its shock /
+# entropy-wave cases (Shu-Osher on 200 cells, Titarev-Toro on 400; domain [0, 10]).
 # ------------------------------------------------------------------------------------------------
 def shock_tube(kind, n=200):
     x = cell_centres(0.0, 1.0, n) if kind in ("sod", "lax") else cell_centres(0.0, 10.0, n)
@@ -247,6 +296,11 @@ def shock_tube(kind, n=200):
         rho = np.where(left, 3.8571, 1.0 + 0.2 * np.sin(5.0 * x))
         u = np.where(left, 2.6294, 0.0); p = np.where(left, 10.3333, 1.0)
         t_end, x1 = 1.8, 10.0
+    elif kind == "titarev_toro":
+        left = x <= 0.5
+        rho = np.where(left, 1.515695, 1.0 + 0.1 * np.sin(20.0 * np.pi * x))
+        u = np.where(left, 0.523346, 0.0); p = np.where(left, 1.80500, 1.0)
+        t_end, x1 = 5.0, 10.0
     else:
         raise ValueError(kind)
     return Problem(kind, EULER1D, n, 1, 0.0, x1, 0.0, 1.0, OUTFLOW, OUTFLOW, conserved_1d(rho, u, p),

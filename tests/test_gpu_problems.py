@@ -1,6 +1,7 @@
 """The paper's one-dimensional Euler problems (section "One dimensional Euler equations": Sod and
-Lax shock tubes, the Shu-Osher shock/entropy-wave interaction) and its Burgers case, run on the GPU
-to about the paper's end times with its CFL number, against the oracle run step for step.
+Lax shock tubes, the Shu-Osher and Titarev-Toro shock/entropy-wave interactions), its Burgers case and
+its linear-advection data u1, u2, u3, run on the GPU to about the paper's end times with its CFL
+number, against the oracle run step for step.
 
 The paper's reference solutions are figures only, so these runs are pinned by oracle parity over the
 whole trajectory, positivity, and conservation while no wave has reached an outflow boundary.
@@ -32,9 +33,9 @@ def _euler_flux(U):
     return np.array([m, m * u + p, u * (E + p)])
 
 
-@pytest.mark.parametrize("kind", ["sod", "lax", "shu_osher"])
+@pytest.mark.parametrize("kind", ["sod", "lax", "shu_osher", "titarev_toro"])
 def test_shock_tube_runs(kind):
-    pr = W.shock_tube(kind, n=200)
+    pr = W.shock_tube(kind, n=400 if kind == "titarev_toro" else 200)
     nsteps = _steps_to(pr, pr.meta["t_end"])
     print("[case]", kind, nsteps, "steps", flush=True)
     Uo, rec = O.run(oracle_cfg(pr), pr.U0, nsteps, cfl=pr.cfl, record=True)
@@ -71,3 +72,25 @@ def test_burgers_to_after_the_shock():
     Ug = U.cpu().numpy()
     assert np.abs(Ug - Uo).max() < 1e-10
     assert abs(Ug.sum() - pr.U0.sum()) < 1e-12 * pr.nx
+
+
+@pytest.mark.parametrize("kind", ["u1", "u2", "u3"])
+def test_paper_advection_one_period(kind):
+    """One period at N = 200, CFL 0.2: the GPU equals the oracle; the smooth data come back to within
+    the RK3-limited error, the four-wave data stay within 1 % of their range (no oscillations)."""
+    pr = W.paper_advection(kind, 200)
+    print("[case] advection", kind, pr.nsteps, "steps", flush=True)
+    Uo = O.run(oracle_cfg(pr), pr.U0, pr.nsteps, dt=pr.dt)
+    sv = solver_for(pr)
+    U = torch.from_numpy(pr.U0.copy()).cuda()
+    sv.run(U, pr.nsteps, dt=pr.dt, graph=True)
+    sv.poll()
+    Ug = U.cpu().numpy()[0, 0]
+    assert np.abs(Ug - Uo[0, 0]).max() < 1e-12
+    err = np.abs(Ug - pr.U0[0, 0])          # after whole periods the exact solution is the data
+    if kind == "u1":
+        assert err.max() < 1e-4, err.max()
+    elif kind == "u2":
+        assert err.max() < 5e-6, err.max()
+    else:
+        assert -0.01 < Ug.min() and Ug.max() < 1.01, (Ug.min(), Ug.max())
