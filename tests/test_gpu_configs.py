@@ -15,6 +15,7 @@ import pytest
 import torch
 
 from oracle import oracle as O
+from paper_1808_00037_amd import teno as T
 from paper_1808_00037_amd import workloads as W
 
 from gpu_common import oracle_cfg, solver_for
@@ -45,6 +46,51 @@ def test_advection_to_t2_at_three_resolutions():
     orders = [math.log2(errs[k][0] / errs[k + 1][0]) for k in range(2)]
     print("[case] L1/Linf", errs, "orders", orders, flush=True)
     assert all(2.8 < o < 3.6 for o in orders), orders
+
+
+def _order(e):
+    return [math.log2(e[k] / e[k + 1]) for k in range(len(e) - 1)]
+
+
+def test_rhs_convergence_orders_on_the_gpu():
+    """The GPU operator on the two-mode advection wave against the exact derivative -u0': order 7 for
+    TENO7X, about 5 for the TENO5 base (eps = dx^3), and equal to the oracle's operator."""
+    errs7, errs5 = [], []
+    for n in (50, 100, 200):
+        pr = W.advection(2, n)
+        x = W.cell_centres(-1.0, 1.0, n)
+        phi = pr.meta["phi"]
+        exact = -(math.pi * np.cos(math.pi * x) + 0.9 * math.pi * np.cos(3 * math.pi * x + phi))
+        U = torch.from_numpy(pr.U0.copy()).cuda()
+        for scheme, eps, errs in ((T.TENO7X, None, errs7), (T.TENO5, (2.0 / n) ** 3, errs5)):
+            sv = solver_for(pr, scheme=scheme, eps=eps)
+            r = sv.rhs(U).cpu().numpy()[0, 0]
+            sv.poll()
+            ro = O.rhs(oracle_cfg(pr, scheme=O.TENO7X if scheme == T.TENO7X else O.TENO5, eps=eps), pr.U0)[0, 0]
+            assert np.abs(r - ro).max() < 1e-12 * np.abs(ro).max()
+            errs.append(np.abs(r - exact).max())
+    o7, o5 = _order(errs7), _order(errs5)
+    print("[case] RHS orders", o7, o5, flush=True)
+    assert min(o7) > 6.5, o7
+    assert 4.5 < min(o5) and max(o5) < 5.6, o5
+
+
+def test_trajectory_order_seven_with_refined_time_step_on_the_gpu():
+    """To t = 2 with dt = 0.2 dx (dx/0.04)^(4/3), so that the RK3 error falls like dx^7."""
+    errs = []
+    for n in (50, 100, 200):
+        pr = W.advection(4, n)
+        dt0 = 0.2 * pr.dx * (pr.dx / 0.04) ** (4.0 / 3.0)
+        nsteps = int(math.ceil(2.0 / dt0))
+        dt = 2.0 / nsteps
+        sv = solver_for(pr)
+        U = torch.from_numpy(pr.U0.copy()).cuda()
+        sv.run(U, nsteps, dt=dt, graph=True)
+        sv.poll()
+        errs.append(np.abs(U.cpu().numpy()[0, 0] - W.advection_exact(pr, 2.0)).mean())
+    o = _order(errs)
+    print("[case] trajectory L1", errs, "orders", o, flush=True)
+    assert min(o) > 6.3, (errs, o)
 
 
 def test_euler1d_4096_2000_steps():
