@@ -1,6 +1,6 @@
 /*
  * teno_oracle.c -- plain CPU reference (the "oracle") of the TENO7X semi-discrete operator and its
- * SSP-RK3 driver, in double precision.
+ * SSP-RK3 time stepping, in double precision.
  *
  * TEST INFRASTRUCTURE. Only the test-suite, the package's smoke check and the CPU-baseline leg of
  * the benchmark may load this library. It shares no code, header, table or helper with the GPU

@@ -2,7 +2,7 @@
 
 Argument marshalling only: every step of the operator, the time stepper, the adjoint and the
 batched runs executes in the HIP kernels of libteno.so. torch provides device memory and the
-current stream. There is no CPU fallback: without the built library on a GPU machine every call fails.
+current stream. There is no CPU fallback: without the built library every call fails.
 
 States are torch tensors on the GPU, shape [nvar, ny, nx], contiguous, float64 (or float32 for
 single-precision contexts); conserved variables (rho, rho u, [rho v], E).
