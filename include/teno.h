@@ -197,7 +197,9 @@ size_t teno_batch_offset(const teno_batch *b, int32_t k);
  * block), the whole run captured once in a HIP graph and replayed; mode 1: one launch per
  * instance per kernel (reference form).
  * U_dev: the packed state of teno_batch_total_elems() elements. Both modes give bitwise equal
- * results. */
+ * results. Unless teno_batch_set_shape() fixed it, the first mode-0 run picks the launch shape:
+ * it advances a temporary copy of the state (allocated and freed inside the call, synchronising
+ * the stream) by a warm-up and three timed steps per candidate shape and keeps the fastest. */
 teno_status teno_batch_run(teno_batch *b, void *U_dev, int32_t nsteps, int32_t mode);
 
 /* Fix mode 0's launch shape instead of letting the first mode-0 run pick it by timing:

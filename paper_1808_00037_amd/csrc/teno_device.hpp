@@ -345,14 +345,16 @@ __device__ __forceinline__ int table3_rev(unsigned r)
 // Five-point cut-off of one split side (eq:smooth_expl, eq:tau5, eq:TENO1 with C = 1, q = 6,
 // eq:norm, eq:seclect). (a..e) = values at i-2..i+2 in upwind order.
 //
-// smooth5() computes beta_0..2 and tau5 = |beta_0 - beta_2|. Exact shortcut: with
-// r_k = 1 + tau5/(beta_k + eps) >= 1, the smallest chi_k is at least
+// smooth5() computes B_k = 4 beta_k and 4 tau5 = |B_0 - B_2|. The cut-off and the shortcut below
+// depend on the measures only through tau5 / (beta_k + eps), so the kernels carry the measures four
+// times larger together with eps4 = 4 eps (a power of two: the same ratios).
+// Exact shortcut: with r_k = 1 + tau5/(beta_k + eps) >= 1, the smallest chi_k is at least
 // 1 / (1 + 2 (r_max/r_min)^6); if tau5 <= K (min_k beta_k + eps) then r_max/r_min <= 1 + K and
 // chi_min >= 1 / (1 + 2 (1 + K)^6). K is chosen on the host from C_T (smooth_shortcut_k) with a
 // margin that covers rounding, so every delta_k = 1 on that branch (C_T = 1e-5: K = 5.0, chi_min
-// >= 1/93313).
+// >= 1/93313). The test is evaluated as 4 tau5 <= K min_k B_k + K eps4, with K eps4 from the host.
 // cutoff3() evaluates the definition: delta_k = 0 iff gamma_k / sum(gamma) < C_T, computed as
-// gamma_k < C_T * sum(gamma) with gamma_k = (1 + tau (D_j D_l) / (D0 D1 D2))^6, D_k = beta_k + eps:
+// gamma_k < C_T * sum(gamma) with gamma_k = (1 + tau (D_j D_l) / (D0 D1 D2))^6, D_k = B_k + eps4:
 // one reciprocal per side instead of six divisions; equal to the definition up to rounding, so a
 // flag can differ from a straight evaluation only when chi_k lies within rounding of C_T.
 // ------------------------------------------------------------------------------------------------
@@ -361,29 +363,32 @@ template <typename T> struct Smooth { T b0, b1, b2, tau; };
 template <typename T>
 __device__ __forceinline__ Smooth<T> smooth5(T a, T b, T c, T d, T e)
 {
-    // eq:smooth_expl regrouped: beta_k = p_k^2 + (13/12) u_k^2 with the second differences u_k and
-    // p_k = half the one-sided first differences, which share the u_k:
-    //   p0 = (a - 4b + 3c)/2 = u0/2 + (c - b),  p1 = (b - d)/2,  p2 = (3c - 4d + e)/2 = u2/2 + (c - d)
-    const T u0 = fma(T(-2), b, a) + c;
-    const T u1 = fma(T(-2), c, b) + d;
-    const T u2 = fma(T(-2), d, c) + e;
-    const T p0 = fma(T(0.5), u0, c - b);
-    const T p1 = T(0.5) * (b - d);
-    const T p2 = fma(T(0.5), u2, c - d);
-    constexpr T K = T(13.0 / 12.0);
+    // eq:smooth_expl regrouped: 4 beta_k = q_k^2 + (13/3) u_k^2 with the second differences u_k and
+    // the one-sided first differences q_k, all from the central differences x = c - b, y = c - d:
+    //   u0 = a - 2b + c = (a - b) + x,  u1 = b - 2c + d = -(x + y),  u2 = c - 2d + e = (e - d) + y,
+    //   q0 = a - 4b + 3c = u0 + 2x,     q1 = b - d = y - x,          q2 = 3c - 4d + e = u2 + 2y
+    // (u1 enters squared, so its sign is dropped)
+    const T x = c - b, y = c - d;
+    const T u0 = (a - b) + x;
+    const T u1 = x + y;
+    const T u2 = (e - d) + y;
+    const T q0 = fma(T(2), x, u0);
+    const T q1 = y - x;
+    const T q2 = fma(T(2), y, u2);
+    constexpr T K = T(13.0 / 3.0);
     Smooth<T> r;
-    r.b0 = fma(K * u0, u0, p0 * p0);
-    r.b1 = fma(K * u1, u1, p1 * p1);
-    r.b2 = fma(K * u2, u2, p2 * p2);
+    r.b0 = fma(K * u0, u0, q0 * q0);
+    r.b1 = fma(K * u1, u1, q1 * q1);
+    r.b2 = fma(K * u2, u2, q2 * q2);
     r.tau = fabs(r.b0 - r.b2);
     return r;
 }
 
 template <typename T>
-__device__ __forceinline__ bool all_smooth(const Smooth<T> &m, T eps, T k)
+__device__ __forceinline__ bool all_smooth(const Smooth<T> &m, T k, T keps4)
 {
     T bmin = fmin(m.b0, fmin(m.b1, m.b2));
-    return m.tau <= k * (bmin + eps);
+    return m.tau <= fma(k, bmin, keps4);
 }
 
 // Largest K of the shortcut for cut-off ct: 1 / (1 + 2 (1 + K)^6) >= ct must hold with room for
@@ -436,9 +441,9 @@ template <typename T> __device__ __forceinline__ T fast_sqrt(T x)
     return s;
 }
 
-__device__ __forceinline__ unsigned cutoff3(const Smooth<double> &m, double eps, double ct)
+__device__ __forceinline__ unsigned cutoff3(const Smooth<double> &m, double eps4, double ct)
 {
-    double D0 = m.b0 + eps, D1 = m.b1 + eps, D2 = m.b2 + eps;
+    double D0 = m.b0 + eps4, D1 = m.b1 + eps4, D2 = m.b2 + eps4;
     double D01 = D0 * D1;
     double tinv = m.tau * recip(D01 * D2);
     double r0 = 1.0 + tinv * (D1 * D2);
@@ -453,9 +458,9 @@ __device__ __forceinline__ unsigned cutoff3(const Smooth<double> &m, double eps,
 }
 
 // Single precision: gamma_k / gamma_max keeps every term in [0, 1] (no overflow of r^6).
-__device__ __forceinline__ unsigned cutoff3(const Smooth<float> &m, float eps, float ct)
+__device__ __forceinline__ unsigned cutoff3(const Smooth<float> &m, float eps4, float ct)
 {
-    float r0 = 1.0f + m.tau / (m.b0 + eps), r1 = 1.0f + m.tau / (m.b1 + eps), r2 = 1.0f + m.tau / (m.b2 + eps);
+    float r0 = 1.0f + m.tau / (m.b0 + eps4), r1 = 1.0f + m.tau / (m.b1 + eps4), r2 = 1.0f + m.tau / (m.b2 + eps4);
     float rm = fmaxf(r0, fmaxf(r1, r2));
     float q0 = r0 / rm, q1 = r1 / rm, q2 = r2 / rm;
     float g0 = q0 * q0 * q0, g1 = q1 * q1 * q1, g2 = q2 * q2 * q2;
@@ -578,8 +583,10 @@ template <typename T> struct SweepArgs {
     int bc;                     // boundary condition along the sweep
     int bc_other;               // (unused by the sweep itself)
     int mode, stage, scheme, alpha_mode;
-    T inv_h, eps, ct, gamma, adv;
+    T inv_h, ct, gamma, adv;
+    T eps4;                     // 4 eps: the eps of the measures as smooth5() scales them
     T smooth_k;                 // all-smooth shortcut factor for ct (smooth_shortcut_k)
+    T keps4;                    // smooth_k * eps4
     T gm1;                      // gamma - 1
     T inv_dx, inv_dy;           // for the CFL denominator of the produced state
 };
@@ -1125,7 +1132,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
                 // (lanes of a packed wave that no piece needs count as smooth: their stencils straddle
                 // two lines)
                 // (both sides evaluated, without a branch between them)
-                const bool easy = (all_smooth(sp, a.eps, a.smooth_k) & all_smooth(sm, a.eps, a.smooth_k)) | !needed;
+                const bool easy = (all_smooth(sp, a.smooth_k, a.keps4) & all_smooth(sm, a.smooth_k, a.keps4)) | !needed;
                 if (__all(easy)) {
                     // every flag of every face of the wave is 1: the full stencil on both sides
                     fword |= 63u << (6 * sf);
@@ -1136,8 +1143,8 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
                         mp = mm = TENO5_ROW[7];
                     }
                 } else {
-                    unsigned dp = easy ? 7u : cutoff3(sp, a.eps, a.ct);
-                    unsigned dm = easy ? 7u : cutoff3(sm, a.eps, a.ct);
+                    unsigned dp = easy ? 7u : cutoff3(sp, a.eps4, a.ct);
+                    unsigned dm = easy ? 7u : cutoff3(sm, a.eps4, a.ct);
                     unsigned bits = dp | (dm << 3);
                     fword |= bits << (6 * sf);
                     if (a.scheme == 0) {

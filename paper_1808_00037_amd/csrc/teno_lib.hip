@@ -128,9 +128,11 @@ static void launch_sweep_t(teno_ctx *c, const SweepReq &r)
     a.scheme = c->opts.scheme;
     a.alpha_mode = c->opts.alpha_mode;
     a.inv_h = (T)(1.0 / (DIR == 0 ? c->dx : c->dy));
-    a.eps = (T)(DIR == 0 ? c->eps_x : c->eps_y);
+    const double eps = DIR == 0 ? c->eps_x : c->eps_y, sk = smooth_shortcut_k(c->opts.ct);
     a.ct = (T)c->opts.ct;
-    a.smooth_k = (T)smooth_shortcut_k(c->opts.ct);
+    a.eps4 = (T)(4.0 * eps);
+    a.smooth_k = (T)sk;
+    a.keps4 = (T)(sk * (4.0 * eps));
     a.gamma = (T)c->opts.gamma;
     a.gm1 = (T)(c->opts.gamma - 1.0);
     a.adv = (T)c->opts.adv_speed;
