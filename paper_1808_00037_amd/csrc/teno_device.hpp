@@ -892,8 +892,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
             T E = a.U[(size_t)(NV - 1) * ncell + off];
             T sq, rs;
             sqrt_rsqrt(rho, sq, rs);
-            T ir = rs * rs;
-            if (!(rho > T(0))) ir = T(1) / rho;
+            T ir = rs * rs;               // (rho <= 0 or NaN: rs is NaN, reported below and at the faces)
             T un = mn * ir, ut = mt * ir;
             T p = a.gm1 * (E - T(0.5) * rho * (un * un + ut * ut));
             if (!(rho > T(0) && p > T(0))) bad |= (isfinite(rho) && isfinite(p)) ? ERR_NONPHYSICAL : ERR_NONFINITE;
