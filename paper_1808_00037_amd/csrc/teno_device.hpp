@@ -1232,26 +1232,43 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
                 size_t off = DIR == 0 ? (size_t)eline * a.nx + fe : (size_t)fe * a.nx + eline;
                 const T *e = ext + (size_t)s * 2 * NV * WAVE + k;
                 T unew[NV];
+                // every field's operands are read before any of the arithmetic, so that the reads
+                // overlap instead of waiting field by field
+                T dv[NV];
 #pragma unroll
-                for (int v = 0; v < NV; ++v) {
-                    const size_t go = (size_t)gvar<SYS, DIR>(v) * ncell + off;
-                    T d = -(Fr[v] - Fh[v]) * a.inv_h;
-                    if (a.addend) d = d + (HAS_EXT ? e[(NV + v) * WAVE] : a.addend[go]);
-                    if constexpr (STAGE_OUT) {
-                        rec[s * SEG_STRIDE + v * OUTW + k - 1] = d;   // own record, no longer read
-                    } else if constexpr (MODE == MODE_RHS) {
-                        a.out[go] = d;
-                    } else {
-                        // SSP-RK3 stage, Shu-Osher form
-                        T uk = R0[FSTR * v + k + 4];   // staged record: conserved variable v first
-                        // U^n: the staged stage input itself at the first stage, else its copy
-                        T u0 = HAS_EXT ? (a.U0 == a.U ? uk : e[v * WAVE]) : a.U0[go];
-                        T dt = (T)dtv;
-                        T un;
-                        if (a.stage == 0) un = u0 + dt * d;
-                        else if (a.stage == 1) un = T(0.75) * u0 + T(0.25) * (uk + dt * d);
-                        else un = T(1.0 / 3.0) * u0 + T(2.0 / 3.0) * (uk + dt * d);
-                        a.out[go] = un;
+                for (int v = 0; v < NV; ++v) dv[v] = -(Fr[v] - Fh[v]) * a.inv_h;
+                if (a.addend) {
+                    T yv[NV];
+#pragma unroll
+                    for (int v = 0; v < NV; ++v)
+                        yv[v] = HAS_EXT ? e[(NV + v) * WAVE] : a.addend[(size_t)gvar<SYS, DIR>(v) * ncell + off];
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) dv[v] = dv[v] + yv[v];
+                }
+                if constexpr (STAGE_OUT) {
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) rec[s * SEG_STRIDE + v * OUTW + k - 1] = dv[v];   // own record, no longer read
+                } else if constexpr (MODE == MODE_RHS) {
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) a.out[(size_t)gvar<SYS, DIR>(v) * ncell + off] = dv[v];
+                } else {
+                    // SSP-RK3 stage, Shu-Osher form: U' = c0 U^n + c1 (U^(k) + dt L) with (c0, c1) =
+                    // (0, 1), (3/4, 1/4), (1/3, 2/3); at the first stage U^(k) is U^n
+                    const T c0 = a.stage == 0 ? T(0) : a.stage == 1 ? T(0.75) : T(1.0 / 3.0);
+                    const T c1 = a.stage == 0 ? T(1) : a.stage == 1 ? T(0.25) : T(2.0 / 3.0);
+                    T ukv[NV], u0v[NV];
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) ukv[v] = R0[FSTR * v + k + 4];   // staged record: conserved variable v first
+                    // U^n: the staged stage input itself at the first stage, else its copy
+#pragma unroll
+                    for (int v = 0; v < NV; ++v)
+                        u0v[v] = HAS_EXT ? (a.U0 == a.U ? ukv[v] : e[v * WAVE]) : a.U0[(size_t)gvar<SYS, DIR>(v) * ncell + off];
+                    const T dt = (T)dtv;
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) {
+                        const T t = fma(dt, dv[v], ukv[v]);
+                        const T un = fma(c0, u0v[v], c1 * t);
+                        a.out[(size_t)gvar<SYS, DIR>(v) * ncell + off] = un;
                         unew[gvar<SYS, DIR>(v)] = un;
                     }
                 }
