@@ -880,16 +880,22 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
         xcontig = id0 % a.nseg + NSEG <= a.nseg && id0 / a.nseg < a.nlines;
         segoff = xcontig ? SEG_CELLS : SEG_LOAD;
     }
-    auto stage_cell = [&](int pos, size_t off) {
+    // a cell's conserved variables (sweep-local order: rho, m_n, [m_t], E), then its record entry
+    auto load_cell = [&](size_t off, T u[NV]) {
+        u[0] = a.U[off];
+        if constexpr (EULER) {
+            u[1] = a.U[(size_t)gvar<SYS, DIR>(1) * ncell + off];
+            if constexpr (NV == 4) u[2] = a.U[(size_t)gvar<SYS, DIR>(2) * ncell + off];
+            u[NV - 1] = a.U[(size_t)(NV - 1) * ncell + off];
+        }
+    };
+    auto put_cell = [&](int pos, const T u[NV]) {
         T *r = rec + pos;
         if constexpr (!EULER) {
-            r[0] = a.U[off];
+            r[0] = u[0];
         } else {
             using S = Rec<SYS>;
-            T rho = a.U[off];
-            T mn = a.U[(size_t)gvar<SYS, DIR>(1) * ncell + off];
-            T mt = NV == 4 ? a.U[(size_t)gvar<SYS, DIR>(2) * ncell + off] : T(0);
-            T E = a.U[(size_t)(NV - 1) * ncell + off];
+            const T rho = u[0], mn = u[1], mt = NV == 4 ? u[2] : T(0), E = u[NV - 1];
             T sq, rs;
             sqrt_rsqrt(rho, sq, rs);
             T ir = rs * rs;               // (rho <= 0 or NaN: rs is NaN, reported below and at the faces)
@@ -906,6 +912,11 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
             r[FSTR * S::RS] = rs;
         }
     };
+    auto stage_cell = [&](int pos, size_t off) {
+        T u[NV];
+        load_cell(off, u);
+        put_cell(pos, u);
+    };
     // epilogue operands of the owned cells (lanes 1..61), staged with the tile so that their
     // latency overlaps the staging instead of the end of the face computation
     constexpr bool HAS_EXT = DIR == 0 && MODE != MODE_FACES && !PACK;
@@ -913,27 +924,49 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
         for (int s = __builtin_amdgcn_readfirstlane(wid); s < NSEG; s += BLOCK / WAVE) {
             const int line0 = pk_l0 + s;                 // piece 0: the wave has no line if absent
             if (line0 >= a.nlines) continue;             // wave-uniform
-            for (int q = lane; q < SEG_LOAD; q += WAVE) {
-                const int i = (q * pk_M) >> 16, ql = q - i * pk_W;
-                int line = pk_l0 + i * NSEG + s;
-                if (i >= pk_P || line >= a.nlines) line = line0;   // idle positions: any valid cell
-                const int g = near ? bc_index_near(pk_c0 - SEG_HALO + ql, a.len, a.bc)
-                                   : bc_index(pk_c0 - SEG_HALO + ql, a.len, a.bc);
-                stage_cell(s * SEG_STRIDE + q, (size_t)line * a.nx + g);
+            constexpr int IT = (SEG_LOAD + WAVE - 1) / WAVE;        // loads first, then conversions
+            T uc[IT][NV];
+#pragma unroll
+            for (int it = 0; it < IT; ++it) {
+                const int q = lane + it * WAVE;
+                if (q < SEG_LOAD) {
+                    const int i = (q * pk_M) >> 16, ql = q - i * pk_W;
+                    int line = pk_l0 + i * NSEG + s;
+                    if (i >= pk_P || line >= a.nlines) line = line0;   // idle positions: any valid cell
+                    const int g = near ? bc_index_near(pk_c0 - SEG_HALO + ql, a.len, a.bc)
+                                       : bc_index(pk_c0 - SEG_HALO + ql, a.len, a.bc);
+                    load_cell((size_t)line * a.nx + g, uc[it]);
+                }
             }
+#pragma unroll
+            for (int it = 0; it < IT; ++it)
+                if (lane + it * WAVE < SEG_LOAD) put_cell(s * SEG_STRIDE + lane + it * WAVE, uc[it]);
         }
     } else if constexpr (PACK) {
-        for (int idx = tid; idx < NSEG * SEG_LOAD; idx += BLOCK) {
-            const int s = idx % NSEG, q = idx / NSEG;
-            const int line0 = pk_l0 + s;
-            if (line0 >= a.nlines) continue;
-            const int i = (q * pk_M) >> 16, ql = q - i * pk_W;
-            int line = pk_l0 + i * NSEG + s;
-            if (i >= pk_P || line >= a.nlines) line = line0;
-            const int g = near ? bc_index_near(pk_c0 - SEG_HALO + ql, a.len, a.bc)
-                               : bc_index(pk_c0 - SEG_HALO + ql, a.len, a.bc);
-            stage_cell(s * SEG_STRIDE + q, (size_t)g * a.nx + line);
+        constexpr int NCELL = NSEG * SEG_LOAD, IT = (NCELL + BLOCK - 1) / BLOCK;   // loads first
+        T uc[IT][NV];
+        int pos[IT];
+#pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            const int idx = tid + it * BLOCK;
+            pos[it] = -1;
+            if (idx < NCELL) {
+                const int s = idx % NSEG, q = idx / NSEG;
+                const int line0 = pk_l0 + s;
+                if (line0 < a.nlines) {
+                    const int i = (q * pk_M) >> 16, ql = q - i * pk_W;
+                    int line = pk_l0 + i * NSEG + s;
+                    if (i >= pk_P || line >= a.nlines) line = line0;
+                    const int g = near ? bc_index_near(pk_c0 - SEG_HALO + ql, a.len, a.bc)
+                                       : bc_index(pk_c0 - SEG_HALO + ql, a.len, a.bc);
+                    pos[it] = s * SEG_STRIDE + q;
+                    load_cell((size_t)g * a.nx + line, uc[it]);
+                }
+            }
         }
+#pragma unroll
+        for (int it = 0; it < IT; ++it)
+            if (pos[it] >= 0) put_cell(pos[it], uc[it]);
     } else if constexpr (DIR == 0) {
         if (xcontig) {
             constexpr int NCELL = (NSEG - 1) * SEG_CELLS + SEG_LOAD;
@@ -951,11 +984,20 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
                 seg_of(s, line, c0);
                 if (line < 0) continue;         // wave-uniform
                 const size_t lbase = (size_t)line * a.nx;
-                for (int q = lane; q < SEG_LOAD; q += WAVE) {
-                    const int g = near ? bc_index_near(c0 - SEG_HALO + q, a.len, a.bc)
-                                       : bc_index(c0 - SEG_HALO + q, a.len, a.bc);
-                    stage_cell(s * SEG_LOAD + q, lbase + g);
+                constexpr int IT = (SEG_LOAD + WAVE - 1) / WAVE;    // loads first, then conversions
+                T uc[IT][NV];
+#pragma unroll
+                for (int it = 0; it < IT; ++it) {
+                    const int q = lane + it * WAVE;
+                    if (q < SEG_LOAD) {
+                        const int g = near ? bc_index_near(c0 - SEG_HALO + q, a.len, a.bc)
+                                           : bc_index(c0 - SEG_HALO + q, a.len, a.bc);
+                        load_cell(lbase + g, uc[it]);
+                    }
                 }
+#pragma unroll
+                for (int it = 0; it < IT; ++it)
+                    if (lane + it * WAVE < SEG_LOAD) put_cell(s * SEG_LOAD + lane + it * WAVE, uc[it]);
             }
         }
         for (int s = __builtin_amdgcn_readfirstlane(wid); s < NSEG; s += BLOCK / WAVE) {
@@ -982,14 +1024,29 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
         static_assert(DIR == 0 || (NSEG & (NSEG - 1)) == 0, "y-tiles hold a power-of-two number of columns");
         const int ntile = (a.nlines + NSEG - 1) / NSEG;
         const int line0 = (tile % ntile) * NSEG, c0 = (tile / ntile) * SEG_CELLS;
-        for (int idx = tid; idx < NSEG * SEG_LOAD; idx += BLOCK) {
-            const int s = idx % NSEG, q = idx / NSEG;
-            const int line = line0 + s;
-            if (line >= a.nlines) continue;
-            const int g = near ? bc_index_near(c0 - SEG_HALO + q, a.len, a.bc)
-                               : bc_index(c0 - SEG_HALO + q, a.len, a.bc);
-            stage_cell(s * SEG_STRIDE + q, (size_t)g * a.nx + line);
+        // a thread's cells (up to IT of them) are all loaded before any is converted, so that the
+        // loads' latencies overlap
+        constexpr int NCELL = NSEG * SEG_LOAD, IT = (NCELL + BLOCK - 1) / BLOCK;
+        T uc[IT][NV];
+        int pos[IT];
+#pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            const int idx = tid + it * BLOCK;
+            pos[it] = -1;
+            if (idx < NCELL) {
+                const int s = idx % NSEG, q = idx / NSEG;
+                const int line = line0 + s;
+                if (line < a.nlines) {
+                    const int g = near ? bc_index_near(c0 - SEG_HALO + q, a.len, a.bc)
+                                       : bc_index(c0 - SEG_HALO + q, a.len, a.bc);
+                    pos[it] = s * SEG_STRIDE + q;
+                    load_cell((size_t)g * a.nx + line, uc[it]);
+                }
+            }
         }
+#pragma unroll
+        for (int it = 0; it < IT; ++it)
+            if (pos[it] >= 0) put_cell(pos[it], uc[it]);
     }
     if constexpr (WAVE_LOCAL)
         wave_lds_fence();
