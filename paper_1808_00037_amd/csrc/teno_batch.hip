@@ -73,6 +73,7 @@ template <typename T> struct BatchSweep {
     int mode, stage, ring_next, scheme, alpha_mode;
     int packed;                     // the item lists leave packable ragged segments to the tail items
     T ct, gamma;
+    T gm1;                          // gamma - 1, formed in double as the single-problem solver does
     T smooth_k;                     // all-smooth shortcut factor for ct
 };
 
@@ -125,7 +126,7 @@ __device__ __forceinline__ SweepArgs<T> item_args(const BatchSweep<T> &b, const 
     a.smooth_k = b.smooth_k;
     a.keps4 = (T)(DIR == 0 ? I.keps4_x : I.keps4_y);
     a.gamma = b.gamma;
-    a.gm1 = b.gamma - T(1);
+    a.gm1 = b.gm1;
     a.adv = T(1);
     a.inv_dx = (T)I.inv_dx;
     a.inv_dy = (T)I.inv_dy;
@@ -275,6 +276,7 @@ BatchSweep<T> base_args(const teno_batch *b)
     a.ct = (T)b->opts.ct;
     a.smooth_k = (T)smooth_shortcut_k(b->opts.ct);
     a.gamma = (T)b->opts.gamma;
+    a.gm1 = (T)(b->opts.gamma - 1.0);
     return a;
 }
 

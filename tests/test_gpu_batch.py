@@ -84,3 +84,27 @@ def test_every_launch_shape_gives_the_same_states():
 def test_batch_rejects_scalar_systems():
     with pytest.raises(T.TenoError):
         T.Batch([W.advection(1, 64)])
+
+
+def test_single_precision_batch():
+    # FP32 instances: both modes bitwise equal to each other and to the FP32 single-problem solver,
+    # and within single-precision rounding of the FP64 oracle after a few steps
+    probs = _problems()
+    b = T.Batch(probs, dtype=torch.float32)
+    buf0 = b.pack([torch.from_numpy(p.U0) for p in probs])
+    a = buf0.clone()
+    b.run(a, 3, mode=0)
+    c = buf0.clone()
+    b.run(c, 3, mode=1)
+    b.poll()
+    assert torch.equal(a, c)
+    for k, p in enumerate(probs):
+        sv = solver_for(p, dtype=torch.float32)
+        U = torch.from_numpy(p.U0.astype(np.float32)).cuda()
+        sv.run(U, 3, graph=False)
+        sv.poll()
+        assert torch.equal(b.unpack(a, k), U), k
+    p = probs[7]
+    Uo = O.run(oracle_cfg(p), p.U0, 3, cfl=p.cfl)
+    err = np.abs(b.unpack(a, 7).double().cpu().numpy() - Uo).max() / np.abs(Uo).max()
+    assert err < 1e-4, err
