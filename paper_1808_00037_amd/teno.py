@@ -329,14 +329,17 @@ def probe_fp64_fma(iters=4096):
 class Batch:
     """Many independent Euler problems advanced together (one packed state buffer)."""
 
-    def __init__(self, problems, dtype=torch.float64, cfl=0.5, gamma=1.4):
+    def __init__(self, problems, dtype=torch.float64, cfl=0.5, gamma=1.4, scheme=TENO7X, alpha_mode=0, eps=None,
+                 ct=1e-5):
         n = len(problems)
         grids = (Grid * n)()
         for k, pr in enumerate(problems):
             grids[k] = Grid(pr.sys, pr.nx, pr.ny, pr.bc_x, pr.bc_y, F64 if dtype == torch.float64 else F32,
                             pr.x0, pr.x1, pr.y0, pr.y1)
         o = default_opts()
-        o.cfl, o.gamma = cfl, gamma
+        o.cfl, o.gamma, o.scheme, o.alpha_mode, o.ct = cfl, gamma, scheme, alpha_mode, ct
+        if eps is not None:
+            o.eps_mode, o.eps = 1, float(eps)
         self.dtype = dtype
         self.problems = problems
         self._stream_val = torch.cuda.current_stream().cuda_stream

@@ -108,3 +108,24 @@ def test_single_precision_batch():
     Uo = O.run(oracle_cfg(p), p.U0, 3, cfl=p.cfl)
     err = np.abs(b.unpack(a, 7).double().cpu().numpy() - Uo).max() / np.abs(Uo).max()
     assert err < 1e-4, err
+
+
+@pytest.mark.parametrize("opts", [dict(scheme=T.TENO5), dict(alpha_mode=1), dict(eps=1e-6), dict(ct=1e-4)],
+                         ids=["teno5", "scalar_alpha", "constant_eps", "ct_1e-4"])
+def test_batch_options_match_single_runs(opts):
+    # every scheme option reaches the batched kernels as it reaches the single-problem solver
+    probs = _problems()
+    b = T.Batch(probs, **opts)
+    buf0 = b.pack([torch.from_numpy(p.U0) for p in probs])
+    a = buf0.clone()
+    b.run(a, 3, mode=0)
+    c = buf0.clone()
+    b.run(c, 3, mode=1)
+    b.poll()
+    assert torch.equal(a, c)
+    for k, p in enumerate(probs):
+        sv = solver_for(p, **opts)
+        U = torch.from_numpy(p.U0.copy()).cuda()
+        sv.run(U, 3, graph=False)
+        sv.poll()
+        assert torch.equal(b.unpack(a, k), U), k
