@@ -219,3 +219,40 @@ def test_invalid_arguments_are_rejected():
         T.Solver(T.EULER1D, 16, ny=2)
     with pytest.raises(T.TenoError):
         T.Solver(T.EULER2D, 0, 4)
+
+
+def _fp32_problem(name):
+    if name == "advection":
+        return W.advection(3, 200)
+    if name == "burgers":
+        return W.burgers(160)
+    if name == "euler1d":
+        return W.euler1d(2, n=500)
+    if name == "sod":
+        return W.shock_tube("sod", n=200)
+    pr = W.euler2d(6, n=96, ny=72)
+    if name == "euler2d_outflow":
+        pr.bc_x = pr.bc_y = O.OUTFLOW
+    return pr
+
+
+@pytest.mark.parametrize("scheme", [T.TENO7X, T.TENO5], ids=["teno7x", "teno5"])
+@pytest.mark.parametrize("name", ["advection", "burgers", "euler1d", "sod", "euler2d", "euler2d_outflow"])
+def test_fp32_every_system_against_fp64_oracle(name, scheme):
+    # single precision: the operator and five steps within single-precision error of the FP64 oracle
+    pr = _fp32_problem(name)
+    eps = 1e-6 if scheme == T.TENO5 else None     # (1e-40 is below FP32's normal range)
+    cfg = oracle_cfg(pr, scheme=scheme, eps=eps)
+    sv = solver_for(pr, dtype=torch.float32, scheme=scheme, eps=eps)
+    U = torch.from_numpy(pr.U0.astype(np.float32)).cuda()
+    rg = sv.rhs(U).double().cpu().numpy()
+    sv.poll()
+    ro = O.rhs(cfg, pr.U0)
+    rel = np.abs(rg - ro).sum() / np.abs(ro).sum()
+    sv.run(U, 5, graph=False)
+    sv.poll()
+    Uo = O.run(cfg, pr.U0, 5, cfl=pr.cfl)
+    rel_u = np.abs(U.double().cpu().numpy() - Uo).sum() / np.abs(Uo).sum()
+    _print_case(name, scheme, rel, rel_u)
+    assert rel < 1e-4, rel          # (measured at most 8e-6)
+    assert rel_u < 1e-6, rel_u      # (measured at most 1.3e-7)
