@@ -256,3 +256,23 @@ def test_fp32_every_system_against_fp64_oracle(name, scheme):
     _print_case(name, scheme, rel, rel_u)
     assert rel < 1e-4, rel          # (measured at most 8e-6)
     assert rel_u < 1e-6, rel_u      # (measured at most 1.3e-7)
+
+
+def test_graph_replays_with_eager_work_between():
+    # the captured step graph replayed several times, with stand-alone evaluations on the same
+    # context between the replays, equals the eager launches after every replay
+    pr = W.euler2d(3, n=80, ny=64)
+    sv = solver_for(pr)
+    ref = solver_for(pr)
+    Ug = torch.from_numpy(pr.U0.copy()).cuda()
+    Ue = torch.from_numpy(pr.U0.copy()).cuda()
+    for rep in range(4):
+        sv.run(Ug, 3, graph=True)          # captured at the first call, replayed afterwards
+        d = sv.rhs(Ug.clone())             # eager work on the same context between replays
+        ref.run(Ue, 3, graph=False)
+        torch.cuda.synchronize()
+        sv.poll()
+        ref.poll()
+        assert torch.isfinite(d).all()
+        assert torch.equal(Ug, Ue), rep
+        assert sv.last_dt() == ref.last_dt(), rep
