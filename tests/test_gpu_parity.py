@@ -276,3 +276,20 @@ def test_graph_replays_with_eager_work_between():
         assert torch.isfinite(d).all()
         assert torch.equal(Ug, Ue), rep
         assert sv.last_dt() == ref.last_dt(), rep
+
+
+@pytest.mark.parametrize("nx,ny", [(60, 62), (61, 61), (62, 60), (122, 123), (244, 9), (245, 5), (9, 244), (183, 17)])
+@pytest.mark.parametrize("bc", [O.PERIODIC, O.OUTFLOW], ids=["periodic", "outflow"])
+def test_euler2d_sizes_around_segment_and_tile_edges(nx, ny, bc):
+    # a segment is 61 cells and an x-tile 4 segments: lines one cell short of, at, and past those
+    # lengths, and tiles that cross line ends
+    pr = W.euler2d(nx + ny, n=nx, ny=ny)
+    pr.bc_x = pr.bc_y = bc
+    assert_face_parity(compare_faces(pr, pr.U0))
+
+
+@pytest.mark.parametrize("n", [60, 62, 122, 244, 245])
+def test_euler1d_periodic_sizes_around_segment_edges(n):
+    pr = W.euler1d(n, n=n)
+    pr.bc_x = O.PERIODIC
+    assert_face_parity(compare_faces(pr, pr.U0))
