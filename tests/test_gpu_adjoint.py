@@ -215,3 +215,28 @@ def test_adjoint_rejects_single_precision():
     a = torch.zeros(8, dtype=torch.float64, device="cuda")
     with pytest.raises(T.TenoError):
         sv.rhs_vjp(U, m, a, U.clone())
+
+
+@pytest.mark.parametrize("shape", [(56, 1), (57, 1), (113, 1), (56, 57), (57, 56), (113, 30), (30, 113)])
+@pytest.mark.parametrize("bc", [O.PERIODIC, O.OUTFLOW], ids=["periodic", "outflow"])
+def test_rhs_vjp_dot_product_sizes(shape, bc):
+    # a backward wave owns 56 cells: lines one short of, at and past multiples of that, 1D and 2D,
+    # against the oracle's forward derivative: <lam, J d> = <J^T lam, d>
+    nx, ny = shape
+    pr = W.euler1d(nx, n=nx) if ny == 1 else W.euler2d(nx + ny, n=nx, ny=ny)
+    pr.bc_x = pr.bc_y = bc
+    cfg, ex, masks = _frozen_inputs(pr, pr.U0)
+    sv = solver_for(pr)
+    rng = np.random.default_rng(nx * 1000 + ny)
+    Ug = torch.from_numpy(pr.U0).cuda()
+    mg = torch.from_numpy(masks.view(np.int32)).cuda()
+    ag = torch.from_numpy(ex["alpha"]).cuda()
+    for _ in range(2):
+        lam = rng.standard_normal(pr.U0.shape)
+        d = W.random_directions(int(rng.integers(1 << 30)), pr.U0, 1)[0]
+        jd = O.rhs_frozen_jvp(cfg, pr.U0, d, ex["alpha"], ex["masks_x"], ex.get("masks_y"))
+        g = sv.rhs_vjp(Ug, mg, ag, torch.from_numpy(lam).cuda()).cpu().numpy()
+        a, b = np.sum(lam * jd), np.sum(g * d)
+        scale = np.sum(np.abs(lam * jd))
+        assert abs(a - b) <= 1e-12 * scale, (a, b)
+    sv.poll()
