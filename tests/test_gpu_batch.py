@@ -129,3 +129,24 @@ def test_batch_options_match_single_runs(opts):
         sv.run(U, 3, graph=False)
         sv.poll()
         assert torch.equal(b.unpack(a, k), U), k
+
+
+def test_batch_of_tiny_and_single_instances():
+    # instances smaller than the stencil (down to one cell), and a batch of one
+    for probs in ([W.euler1d(1, n=1), W.euler1d(2, n=2), W.euler2d(3, n=1, ny=1), W.euler2d(4, n=2, ny=3),
+                   W.euler2d(5, n=7, ny=5), W.euler2d(6, n=3, ny=26)],
+                  [W.euler2d(7, n=90, ny=70)]):
+        b = T.Batch(probs)
+        buf0 = b.pack([torch.from_numpy(p.U0) for p in probs])
+        a = buf0.clone()
+        b.run(a, 2, mode=0)
+        c = buf0.clone()
+        b.run(c, 2, mode=1)
+        b.poll()
+        assert torch.equal(a, c)
+        for k, p in enumerate(probs):
+            sv = solver_for(p)
+            U = torch.from_numpy(p.U0.copy()).cuda()
+            sv.run(U, 2, graph=False)
+            sv.poll()
+            assert torch.equal(b.unpack(a, k), U), (len(probs), k)
