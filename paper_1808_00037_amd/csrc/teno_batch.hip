@@ -414,13 +414,25 @@ teno_status run_t(teno_batch *b, T *U, int nsteps, int mode)
         return hipGetLastError() == hipSuccess ? TENO_OK : TENO_E_HIP;
     }
     if (!b->tuned) {
-        // autotune on a scratch copy of the batch: candidates (x-tile, y-tile)
-        T *tmp = nullptr;
-        HIP_TRY(hipMalloc(&tmp, b->total * sizeof(T)));
+        // autotune on a scratch copy of the batch: candidates (x-tile, y-tile, packing); the scratch
+        // copy and the events are released on every path out of this block (hipFree waits for the
+        // device, so no launch still reads the copy)
+        struct TuneScratch {
+            T *tmp = nullptr;
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            ~TuneScratch()
+            {
+                if (e0) (void)hipEventDestroy(e0);
+                if (e1) (void)hipEventDestroy(e1);
+                if (tmp) (void)hipFree(tmp);
+            }
+        } ts;
+        HIP_TRY(hipMalloc(&ts.tmp, b->total * sizeof(T)));
+        T *tmp = ts.tmp;
         HIP_TRY(hipMemcpyAsync(tmp, U, b->total * sizeof(T), hipMemcpyDeviceToDevice, b->stream));
-        hipEvent_t e0, e1;
-        HIP_TRY(hipEventCreate(&e0));
-        HIP_TRY(hipEventCreate(&e1));
+        HIP_TRY(hipEventCreate(&ts.e0));
+        HIP_TRY(hipEventCreate(&ts.e1));
+        hipEvent_t e0 = ts.e0, e1 = ts.e1;
         float best = 1e30f;
         int bvx = 0, bvy = 1, bp = 0;
         for (int p = 0; p < 2; ++p)
@@ -443,9 +455,6 @@ teno_status run_t(teno_batch *b, T *U, int nsteps, int mode)
                     }
                     if (fastest < best) { best = fastest; bvx = vx; bvy = vy; bp = p; }
                 }
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
-        HIP_TRY(hipFree(tmp));
         b->vx = bvx;
         b->vy = bvy;
         b->pk = bp;

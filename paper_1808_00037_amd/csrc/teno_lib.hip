@@ -320,10 +320,21 @@ void teno_enqueue_step(teno_ctx *c, void *U, double dt_fixed, const double *froz
 teno_status teno_ensure_scratch(teno_ctx *c)
 {
     if (c->S1) return TENO_OK;
-    size_t bytes = c->nelem * c->esize;
-    HIP_TRY(hipMalloc(&c->S1, bytes));
-    HIP_TRY(hipMalloc(&c->S2, bytes));
-    if (c->grid.sys == TENO_EULER2D) HIP_TRY(hipMalloc(&c->dUy, bytes));
+    const size_t bytes = c->nelem * c->esize;
+    void *s1 = nullptr, *s2 = nullptr, *dy = nullptr;
+    bool ok = hipMalloc(&s1, bytes) == hipSuccess && hipMalloc(&s2, bytes) == hipSuccess &&
+              (c->grid.sys != TENO_EULER2D || hipMalloc(&dy, bytes) == hipSuccess);
+    if (!ok) {
+        // all or nothing: a later call must not find a partial set
+        (void)hipFree(s1);
+        (void)hipFree(s2);
+        (void)hipFree(dy);
+        (void)hipGetLastError();
+        return TENO_E_HIP;
+    }
+    c->S1 = s1;
+    c->S2 = s2;
+    c->dUy = dy;
     return TENO_OK;
 }
 
