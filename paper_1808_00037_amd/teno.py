@@ -109,6 +109,19 @@ def _stream():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
+_WORD_TYPES = (torch.int32,) + ((torch.uint32,) if hasattr(torch, "uint32") else ())
+
+
+def _buf(t, dtypes, numel, what):
+    """A device buffer the library writes or reads by pointer: contiguous, on the GPU, of one of
+    dtypes and with at least numel elements (the C ABI cannot check sizes)."""
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.is_contiguous() and t.dtype in dtypes
+            and t.numel() >= numel):
+        names = "/".join(str(d).replace("torch.", "") for d in dtypes)
+        raise ValueError(f"{what} must be a contiguous {names} CUDA tensor of at least {numel} elements")
+    return t
+
+
 def default_opts():
     o = Opts()
     lib().teno_default_opts(ctypes.byref(o))
@@ -179,6 +192,8 @@ class Solver:
         self._sync_stream()
         U = self._state(U)
         out = self.empty_state() if out is None else self._state(out)
+        if masks is not None:
+            _buf(masks, _WORD_TYPES, self.nfaces, "masks")
         _check(lib().teno_rhs(self._h, _ptr(U), _ptr(out), _ptr(masks)), "teno_rhs")
         return out
 
@@ -203,6 +218,8 @@ class Solver:
         self._sync_stream()
         U = self._state(U)
         out = self.empty_state() if out is None else self._state(out)
+        _buf(masks, _WORD_TYPES, self.nfaces, "masks")
+        _buf(alpha, (torch.float64,), 8, "alpha")
         _check(lib().teno_rhs_frozen(self._h, _ptr(U), _ptr(masks), _ptr(alpha), _ptr(out)), "teno_rhs_frozen")
         return out
 
@@ -243,7 +260,9 @@ class Solver:
     # ------------------------------------------------------------------ frozen-selection adjoint
     def rhs_vjp(self, U, masks, alpha, lam, out=None):
         self._sync_stream()
-        out = self.empty_state() if out is None else out
+        out = self.empty_state() if out is None else self._state(out)
+        _buf(masks, _WORD_TYPES, self.nfaces, "masks")
+        _buf(alpha, (torch.float64,), 8, "alpha")
         _check(lib().teno_rhs_vjp(self._h, _ptr(self._state(U)), _ptr(masks), _ptr(alpha), _ptr(self._state(lam)),
                                   _ptr(out)), "teno_rhs_vjp")
         return out
@@ -262,6 +281,10 @@ class Solver:
     def run_replay(self, U, rec, nsteps=None):
         self._sync_stream()
         n = rec["nsteps"] if nsteps is None else nsteps
+        if not 0 <= n <= rec["nsteps"]:
+            raise ValueError("nsteps exceeds the recording")
+        _buf(rec["masks"], _WORD_TYPES, n * 3 * self.nfaces, "recorded masks")
+        _buf(rec["alpha_dt"], (torch.float64,), n * 25, "recorded alpha/dt")
         _check(lib().teno_run_replay(self._h, _ptr(self._state(U)), int(n), _ptr(rec["masks"]), _ptr(rec["alpha_dt"])),
                "teno_run_replay")
         return U
@@ -269,6 +292,12 @@ class Solver:
     def run_vjp(self, rec, lam):
         """lam: dJ/dU(T) (overwritten in place with dJ/dU(0))."""
         self._sync_stream()
+        n, ck = int(rec["nsteps"]), int(rec["ckpt_every"])
+        if rec["masks"] is None:
+            raise ValueError("the backward pass needs a recording with masks")
+        _buf(rec["ckpt"], (self.dtype,), -(-n // ck) * self.nvar * self.nx * self.ny, "checkpoints")
+        _buf(rec["masks"], _WORD_TYPES, n * 3 * self.nfaces, "recorded masks")
+        _buf(rec["alpha_dt"], (torch.float64,), n * 25, "recorded alpha/dt")
         _check(lib().teno_run_vjp(self._h, _ptr(rec["ckpt"]), _ptr(rec["masks"]), _ptr(rec["alpha_dt"]),
                                   int(rec["nsteps"]), int(rec["ckpt_every"]), _ptr(self._state(lam))), "teno_run_vjp")
         return lam
@@ -364,6 +393,7 @@ class Batch:
     def run(self, buf, nsteps, mode=0):
         if torch.cuda.current_stream().cuda_stream != self._stream_val:
             raise RuntimeError("a Batch runs on the stream it was created on")
+        _buf(buf, (self.dtype,), self.total, "the packed batch state")
         _check(lib().teno_batch_run(self._h, _ptr(buf), int(nsteps), int(mode)), "teno_batch_run")
         return buf
 

@@ -117,3 +117,13 @@ def test_batch_create_rejects_empty_and_null(T):
     h = ctypes.c_void_p()
     assert T.lib().teno_batch_create(grids, 0, ctypes.byref(o), None, ctypes.byref(h)) == -1
     assert T.lib().teno_batch_create(None, 1, ctypes.byref(o), None, ctypes.byref(h)) == -1
+
+
+
+def test_binding_rejects_host_buffers():
+    # the C ABI takes plain device pointers: the binding refuses host tensors before any call
+    import torch
+    from paper_1808_00037_amd.teno import _WORD_TYPES, _buf
+    for bad in (torch.zeros(10, dtype=torch.int32), None, "masks"):
+        with pytest.raises(ValueError):
+            _buf(bad, _WORD_TYPES, 10, "masks")

@@ -293,3 +293,31 @@ def test_euler1d_periodic_sizes_around_segment_edges(n):
     pr = W.euler1d(n, n=n)
     pr.bc_x = O.PERIODIC
     assert_face_parity(compare_faces(pr, pr.U0))
+
+
+def test_binding_checks_buffer_sizes():
+    # buffers the library writes or reads by pointer are checked by the binding before the call
+    pr = W.euler2d(5, n=40, ny=30)
+    sv = solver_for(pr)
+    U = torch.from_numpy(pr.U0.copy()).cuda()
+    good = sv.masks_buffer()
+    for bad in (torch.empty(sv.nfaces - 1, dtype=torch.int32, device="cuda"),
+                torch.empty(sv.nfaces, dtype=torch.float32, device="cuda"),
+                torch.empty(2 * sv.nfaces, dtype=torch.int32, device="cuda")[::2]):
+        with pytest.raises(ValueError):
+            sv.rhs(U, masks=bad)
+        with pytest.raises(ValueError):
+            sv.rhs_frozen(U, bad, sv.last_alpha())
+    sv.rhs(U, masks=good)
+    with pytest.raises(ValueError):
+        sv.rhs_frozen(U, good, torch.zeros(7, dtype=torch.float64, device="cuda"))
+    rec = sv.run_record(U.clone(), 4, 2)
+    with pytest.raises(ValueError):
+        sv.run_replay(U.clone(), rec, nsteps=5)
+    short = dict(rec, alpha_dt=rec["alpha_dt"][:3])
+    with pytest.raises(ValueError):
+        sv.run_vjp(short, torch.zeros_like(U))
+    b = T.Batch([pr])
+    with pytest.raises(ValueError):
+        b.run(torch.zeros(b.total - 1, dtype=torch.float64, device="cuda"), 1)
+    sv.poll()
