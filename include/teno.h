@@ -139,6 +139,19 @@ teno_status teno_poll(teno_ctx *ctx);
 /* dt of the most recent step (synchronises). */
 teno_status teno_last_dt(teno_ctx *ctx, double *dt_host);
 
+/* Simulated time. Every step (teno_step, teno_run, teno_run_record; also the steps of a replayed
+ * graph) advances the context's time t by its dt on the device; a new context starts at t = 0.
+ * Replays of recorded steps (teno_run_replay, the recomputation inside teno_run_vjp) leave t alone.
+ * teno_set_time sets t = t0 and, when t_end > t0, an end time: a step whose dt (from the CFL rule
+ * or dt_fixed) would pass t_end is cut to end exactly there, and steps taken at t = t_end have
+ * dt = 0 and leave the state unchanged bit for bit, so a run of more steps than needed stops at
+ * t_end. t_end <= t0 removes the limit. Stream-ordered; TENO_E_ARG for a non-finite t0 or a NaN
+ * t_end. (The paper runs its problems to fixed end times.) */
+teno_status teno_set_time(teno_ctx *ctx, double t0, double t_end);
+
+/* The simulated time t after the work enqueued so far (synchronises the stream). */
+teno_status teno_get_time(teno_ctx *ctx, double *t_host);
+
 /* Copy (stream-ordered, no synchronisation) the eight Lax-Friedrichs constants of the most recent
  * operator evaluation or stage to alpha_dev (device, 8 doubles: x fields then y fields). */
 teno_status teno_last_alpha(teno_ctx *ctx, double *alpha_dev);

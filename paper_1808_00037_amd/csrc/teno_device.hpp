@@ -83,8 +83,10 @@ struct Ctrl {
     double alpha[8];                           // Lax-Friedrichs constants of the current stage
     double den;                                // CFL denominator of the current stage's state
     double dt;                                 // dt of the current step
+    double t;                                  // simulated time, advanced by every step
+    double t_end;                              // end time of the runs (used when end_on)
     unsigned err;
-    unsigned pad_;
+    unsigned end_on;                           // steps are cut at t_end, and stand still there
 };
 
 // ------------------------------------------------------------------------------------------------
@@ -1311,8 +1313,10 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
                 } else {
                     // SSP-RK3 stage, Shu-Osher form: U' = c0 U^n + c1 (U^(k) + dt L) with (c0, c1) =
                     // (0, 1), (3/4, 1/4), (1/3, 2/3); at the first stage U^(k) is U^n
-                    const T c0 = a.stage == 0 ? T(0) : a.stage == 1 ? T(0.75) : T(1.0 / 3.0);
-                    const T c1 = a.stage == 0 ? T(1) : a.stage == 1 ? T(0.25) : T(2.0 / 3.0);
+                    // (a step of dt = 0, at a run's end time, leaves the state exactly as it is)
+                    const bool still = dtv == 0.0;
+                    const T c0 = (a.stage == 0 || still) ? T(0) : a.stage == 1 ? T(0.75) : T(1.0 / 3.0);
+                    const T c1 = (a.stage == 0 || still) ? T(1) : a.stage == 1 ? T(0.25) : T(2.0 / 3.0);
                     T ukv[NV], u0v[NV];
 #pragma unroll
                     for (int v = 0; v < NV; ++v) ukv[v] = R0[FSTR * v + k + 4];   // staged record: conserved variable v first
@@ -1562,9 +1566,24 @@ static __global__ void prep_kernel(Ctrl *ctrl, int ring, int stage, double dt_fi
         ctrl->den = vals[8];
         if (stage == 0) {
             double dt = dt_fixed > 0.0 ? dt_fixed : cfl / vals[8];
-            if (frozen) dt = frozen[24];
-            if (!(dt > 0.0) || !isfinite(dt)) atomicOr(&ctrl->err, ERR_NONFINITE);
+            double tn = ctrl->t + dt;
+            bool at_end = false;
+            if (frozen) {
+                dt = frozen[24];
+                tn = ctrl->t;               // replays of recorded steps leave the time alone
+                at_end = dt == 0.0;         // (a recorded step at an end time)
+            } else if (ctrl->end_on) {
+                // the step that would pass t_end lands on it exactly; later steps have dt = 0
+                const double rest = ctrl->t_end - ctrl->t;
+                if (!(dt < rest)) {
+                    dt = rest > 0.0 ? rest : 0.0;
+                    tn = ctrl->t_end;
+                    at_end = true;
+                }
+            }
+            if (!(dt > 0.0 || (at_end && dt == 0.0)) || !isfinite(dt)) atomicOr(&ctrl->err, ERR_NONFINITE);
             ctrl->dt = dt;
+            ctrl->t = tn;
             if (record) record[24] = dt;
         }
     }
@@ -1573,6 +1592,16 @@ static __global__ void prep_kernel(Ctrl *ctrl, int ring, int stage, double dt_fi
 static __global__ void clear_ring_kernel(Ctrl *ctrl, int ring)
 {
     for (int q = threadIdx.x; q < NCOPY * NWORD; q += blockDim.x) (&ctrl->part[ring][0][0])[q] = 0ull;
+}
+
+// Simulated time and end time of the runs that follow.
+static __global__ void set_time_kernel(Ctrl *ctrl, double t0, double t_end, unsigned on)
+{
+    if (threadIdx.x == 0) {
+        ctrl->t = t0;
+        ctrl->t_end = t_end;
+        ctrl->end_on = on;
+    }
 }
 
 // Copy the eight constants of the current stage out (parity/debug form).

@@ -581,4 +581,20 @@ teno_status teno_last_dt(teno_ctx *c, double *dt_host)
     return TENO_OK;
 }
 
+teno_status teno_set_time(teno_ctx *c, double t0, double t_end)
+{
+    if (!c || !std::isfinite(t0) || std::isnan(t_end)) return TENO_E_ARG;
+    const unsigned on = t_end > t0 ? 1u : 0u;
+    hipLaunchKernelGGL(set_time_kernel, dim3(1), dim3(64), 0, c->stream, c->ctrl_d, t0, on ? t_end : 0.0, on);
+    return hipGetLastError() == hipSuccess ? TENO_OK : TENO_E_HIP;
+}
+
+teno_status teno_get_time(teno_ctx *c, double *t_host)
+{
+    if (!c || !t_host) return TENO_E_ARG;
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    HIP_TRY(hipMemcpy(t_host, &c->ctrl_d->t, sizeof(double), hipMemcpyDeviceToHost));
+    return TENO_OK;
+}
+
 }  // extern "C"

@@ -63,6 +63,8 @@ _SIGS = {
     "teno_run": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.c_double, ctypes.c_int32]),
     "teno_poll": (ctypes.c_int, [_P]),
     "teno_last_dt": (ctypes.c_int, [_P, _P]),
+    "teno_set_time": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_double]),
+    "teno_get_time": (ctypes.c_int, [_P, _P]),
     "teno_last_alpha": (ctypes.c_int, [_P, _P]),
     "teno_set_timing": (ctypes.c_int, [_P, ctypes.c_int32]),
     "teno_read_timing": (ctypes.c_int, [_P, _P, _P]),
@@ -239,6 +241,17 @@ class Solver:
     def last_dt(self):
         v = ctypes.c_double()
         _check(lib().teno_last_dt(self._h, ctypes.byref(v)), "teno_last_dt")
+        return v.value
+
+    def set_time(self, t0=0.0, t_end=0.0):
+        """Set the simulated time to t0 and, when t_end > t0, stop the runs that follow at t_end
+        (the step that would pass it is cut; later steps leave the state unchanged)."""
+        self._sync_stream()
+        _check(lib().teno_set_time(self._h, float(t0), float(t_end)), "teno_set_time")
+
+    def time(self):
+        v = ctypes.c_double()
+        _check(lib().teno_get_time(self._h, ctypes.byref(v)), "teno_get_time")
         return v.value
 
     def last_alpha(self):
