@@ -1,7 +1,7 @@
 """The paper's one-dimensional Euler problems (section "One dimensional Euler equations": Sod and
 Lax shock tubes, the Shu-Osher and Titarev-Toro shock/entropy-wave interactions), its Burgers case and
-its linear-advection data u1, u2, u3, run on the GPU to about the paper's end times with its CFL
-number, against the oracle run step for step.
+its linear-advection data u1, u2, u3, run on the GPU to the paper's end times with its CFL number
+(the step that would pass the end time is cut to land on it), against the oracle run step for step.
 
 The paper's reference solutions are figures only, so these runs are pinned by oracle parity over the
 whole trajectory, positivity, and conservation while no wave has reached an outflow boundary.
@@ -26,6 +26,30 @@ def _steps_to(pr, t_end):
     return max(1, int(round(t_end / rec["dt"][0])))
 
 
+def _run_to(pr, t_end):
+    """The oracle and the GPU advanced to exactly t_end with the CFL rule: whole steps while they end
+    before t_end, then one step of the remaining time. Returns (oracle state, GPU state, steps)."""
+    cfg = oracle_cfg(pr)
+    n = 2 * _steps_to(pr, t_end) + 10
+    _, rec = O.run(cfg, pr.U0, n, cfl=pr.cfl, record=True)
+    t, m = 0.0, 0
+    while t + rec["dt"][m] < t_end:
+        t += rec["dt"][m]
+        m += 1
+    assert m < n - 1
+    # the end time must not sit within rounding of a step boundary (the two sides' dt agree to ~1e-14)
+    assert min(t_end - t, t + rec["dt"][m] - t_end) > 1e-9 * t_end
+    Uo = O.run(cfg, pr.U0, m, cfl=pr.cfl) if m else pr.U0.copy()
+    Uo = O.run(cfg, Uo, 1, dt=t_end - t)
+    sv = solver_for(pr)
+    U = torch.from_numpy(pr.U0.copy()).cuda()
+    sv.set_time(0.0, t_end)
+    sv.run(U, m + 5, graph=True)
+    sv.poll()
+    assert sv.time() == t_end
+    return Uo, U.cpu().numpy(), m + 1
+
+
 def _euler_flux(U):
     rho, m, E = U
     u = m / rho
@@ -36,40 +60,33 @@ def _euler_flux(U):
 @pytest.mark.parametrize("kind", ["sod", "lax", "shu_osher", "titarev_toro"])
 def test_shock_tube_runs(kind):
     pr = W.shock_tube(kind, n=400 if kind == "titarev_toro" else 200)
-    nsteps = _steps_to(pr, pr.meta["t_end"])
-    print("[case]", kind, nsteps, "steps", flush=True)
-    Uo, rec = O.run(oracle_cfg(pr), pr.U0, nsteps, cfl=pr.cfl, record=True)
-    sv = solver_for(pr)
-    U = torch.from_numpy(pr.U0.copy()).cuda()
-    sv.run(U, nsteps, graph=True)
-    sv.poll()
-    Ug = U.cpu().numpy()
+    t_end = pr.meta["t_end"]
+    Uo, Ug, nsteps = _run_to(pr, t_end)
+    print("[case]", kind, nsteps, "steps to t =", t_end, flush=True)
     err = np.abs(Ug - Uo).max() / np.abs(Uo).max()
     assert err < 1e-10, err
     rho, m, E = Ug[0, 0], Ug[1, 0], Ug[2, 0]
     p = 0.4 * (E - 0.5 * m * m / rho)
     assert rho.min() > 0 and p.min() > 0
     if kind in ("sod", "lax"):
-        # no wave reaches either boundary before the end time (the boundary cells keep their states
-        # to within the exponentially small tails), so the totals change only by the boundary
-        # fluxes: sum(U) dx grows by T (F(U_left) - F(U_right))
-        assert np.allclose(Ug[:, 0, [0, -1]], pr.U0[:, 0, [0, -1]], rtol=1e-9, atol=1e-12)
-        t = float(np.sum(rec["dt"]))
-        flux_in = t * (_euler_flux(pr.U0[:, 0, 0]) - _euler_flux(pr.U0[:, 0, -1]))
+        # no wave reaches either boundary before the end time: the boundary cells keep their states
+        # up to the schemes' small tails (Lax's rarefaction head comes within a few cells of the left
+        # boundary by t = 0.14), so the totals change by the boundary fluxes, sum(U) dx grows by
+        # T (F(U_left) - F(U_right)), up to T times the boundary fluxes' drift
+        drift = np.abs(Ug[:, 0, [0, -1]] - pr.U0[:, 0, [0, -1]]).max() / np.abs(pr.U0[:, 0, [0, -1]]).max()
+        print("[case]", kind, "boundary drift", drift, flush=True)
+        assert drift < (1e-12 if kind == "sod" else 1e-8), drift     # (measured 4e-15 and 1.1e-9)
+        flux_in = t_end * (_euler_flux(pr.U0[:, 0, 0]) - _euler_flux(pr.U0[:, 0, -1]))
+        dflux = t_end * (np.abs(_euler_flux(Ug[:, 0, 0]) - _euler_flux(pr.U0[:, 0, 0])) +
+                         np.abs(_euler_flux(Ug[:, 0, -1]) - _euler_flux(pr.U0[:, 0, -1])))
         change = (Ug.sum(axis=(1, 2)) - pr.U0.sum(axis=(1, 2))) * pr.dx
         scale = np.maximum(np.abs(pr.U0).sum(axis=(1, 2)) * pr.dx, np.abs(flux_in))
-        assert np.all(np.abs(change - flux_in) <= 1e-11 * scale), (change, flux_in)
+        assert np.all(np.abs(change - flux_in) <= 1e-11 * scale + dflux), (change, flux_in, dflux)
 
 
 def test_burgers_to_after_the_shock():
     pr = W.burgers(160, cfl=0.6)
-    nsteps = _steps_to(pr, 1.5 / math.pi)
-    Uo = O.run(oracle_cfg(pr), pr.U0, nsteps, cfl=pr.cfl)
-    sv = solver_for(pr)
-    U = torch.from_numpy(pr.U0.copy()).cuda()
-    sv.run(U, nsteps, graph=True)
-    sv.poll()
-    Ug = U.cpu().numpy()
+    Uo, Ug, _ = _run_to(pr, 1.5 / math.pi)
     assert np.abs(Ug - Uo).max() < 1e-10
     assert abs(Ug.sum() - pr.U0.sum()) < 1e-12 * pr.nx
 
