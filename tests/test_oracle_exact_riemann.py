@@ -1,0 +1,164 @@
+"""The oracle's 1D Euler trajectories against the exact solution of the Riemann problem.
+
+The shock tubes of section "One dimensional Euler equations" (Sod, Lax) have a closed-form solution:
+two outer waves (shock or rarefaction) around a contact, with the star-region pressure the root of
+f_L(p) + f_R(p) + u_R - u_L = 0 (the standard construction for the ideal-gas Euler equations). The
+exact solver below is pinned first by the jump conditions it must satisfy (Rankine-Hugoniot across
+shocks, constant entropy and Riemann invariant across rarefactions, equal pressure and velocity
+across the contact); the oracle, run with its own CFL steps to exactly the end time, must then
+approach it in L1 as the grid is refined.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1808_00037_amd import workloads as W
+
+G = 1.4
+
+
+def _f(p, rho, pk, c):
+    """Velocity jump across the wave between a state (rho, pk) and pressure p, and its derivative."""
+    if p > pk:                                    # shock
+        a, b = 2.0 / ((G + 1) * rho), (G - 1) / (G + 1) * pk
+        q = np.sqrt(a / (p + b))
+        return (p - pk) * q, q * (1.0 - 0.5 * (p - pk) / (b + p))
+    e = (G - 1) / (2 * G)                          # rarefaction
+    return 2 * c / (G - 1) * ((p / pk) ** e - 1.0), (p / pk) ** (-(G + 1) / (2 * G)) / (rho * c)
+
+
+def star_state(wl, wr):
+    (rl, ul, pl), (rr, ur, pr) = wl, wr
+    cl, cr = np.sqrt(G * pl / rl), np.sqrt(G * pr / rr)
+    p = max(1e-8, 0.5 * (pl + pr))
+    for _ in range(100):
+        fl, dl = _f(p, rl, pl, cl)
+        fr, dr = _f(p, rr, pr, cr)
+        step = (fl + fr + ur - ul) / (dl + dr)
+        p_new = max(1e-12, p - step)
+        if abs(p_new - p) <= 1e-15 * p_new:
+            p = p_new
+            break
+        p = p_new
+    fl, _ = _f(p, rl, pl, cl)
+    fr, _ = _f(p, rr, pr, cr)
+    return p, 0.5 * (ul + ur) + 0.5 * (fr - fl)
+
+
+def exact(wl, wr, xi):
+    """Primitive state (rho, u, p) of the Riemann solution at the similarity coordinates xi = x/t."""
+    (rl, ul, pl), (rr, ur, pr) = wl, wr
+    cl, cr = np.sqrt(G * pl / rl), np.sqrt(G * pr / rr)
+    ps, us = star_state(wl, wr)
+    g6 = (G - 1) / (G + 1)
+    out = np.zeros((3, xi.size))
+    for i, s in enumerate(xi):
+        if s <= us:
+            if ps > pl:
+                sl = ul - cl * np.sqrt((G + 1) / (2 * G) * ps / pl + (G - 1) / (2 * G))
+                w = (rl, ul, pl) if s <= sl else (rl * (ps / pl + g6) / (g6 * ps / pl + 1), us, ps)
+            else:
+                shl, stl = ul - cl, us - cl * (ps / pl) ** ((G - 1) / (2 * G))
+                if s <= shl:
+                    w = (rl, ul, pl)
+                elif s >= stl:
+                    w = (rl * (ps / pl) ** (1 / G), us, ps)
+                else:
+                    u = 2 / (G + 1) * (cl + (G - 1) / 2 * ul + s)
+                    c = 2 / (G + 1) * (cl + (G - 1) / 2 * (ul - s))
+                    w = (rl * (c / cl) ** (2 / (G - 1)), u, pl * (c / cl) ** (2 * G / (G - 1)))
+        else:
+            if ps > pr:
+                sr = ur + cr * np.sqrt((G + 1) / (2 * G) * ps / pr + (G - 1) / (2 * G))
+                w = (rr, ur, pr) if s >= sr else (rr * (ps / pr + g6) / (g6 * ps / pr + 1), us, ps)
+            else:
+                shr, str_ = ur + cr, us + cr * (ps / pr) ** ((G - 1) / (2 * G))
+                if s >= shr:
+                    w = (rr, ur, pr)
+                elif s <= str_:
+                    w = (rr * (ps / pr) ** (1 / G), us, ps)
+                else:
+                    u = 2 / (G + 1) * (-cr + (G - 1) / 2 * ur + s)
+                    c = 2 / (G + 1) * (cr - (G - 1) / 2 * (ur - s))
+                    w = (rr * (c / cr) ** (2 / (G - 1)), u, pr * (c / cr) ** (2 * G / (G - 1)))
+        out[:, i] = w
+    return out
+
+
+CASES = {
+    "sod": ((1.0, 0.0, 1.0), (0.125, 0.0, 0.1)),
+    "lax": ((0.445, 0.698, 3.528), (0.5, 0.0, 0.571)),
+    "two_shocks": ((1.0, 1.0, 1.0), (1.0, -1.0, 1.0)),
+    "two_rarefactions": ((1.0, -0.5, 1.0), (1.0, 0.5, 1.0)),
+}
+
+
+def _flux(w):
+    rho, u, p = w
+    E = p / (G - 1) + 0.5 * rho * u * u
+    return np.array([rho * u, rho * u * u + p, u * (E + p)]), np.array([rho, rho * u, E])
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_exact_solver_satisfies_the_jump_conditions(name):
+    wl, wr = CASES[name]
+    ps, us = star_state(wl, wr)
+    xi = np.linspace(-4, 4, 8001)
+    sol = exact(wl, wr, xi)
+    # contact: pressure and velocity continuous, and equal to the star values on both sides
+    k = np.searchsorted(xi, us)
+    for j in (k - 2, k + 2):
+        assert abs(sol[2, j] - ps) < 1e-12 * ps and abs(sol[1, j] - us) < 1e-12
+    for side, w0 in (("l", wl), ("r", wr)):
+        rho0, u0, p0 = w0
+        if ps > p0:
+            # shock: Rankine-Hugoniot, F(W1) - F(W0) = S (U(W1) - U(W0)) for the shock speed S
+            star = sol[:, k - 2] if side == "l" else sol[:, k + 2]
+            f0, q0 = _flux(w0)
+            f1, q1 = _flux(star)
+            s = (f1[0] - f0[0]) / (q1[0] - q0[0])
+            assert np.allclose(f1 - f0, s * (q1 - q0), rtol=1e-10, atol=1e-12)
+        else:
+            # rarefaction: p / rho^gamma and u +- 2c/(gamma-1) constant through the fan
+            c0 = np.sqrt(G * p0 / rho0)
+            sign = 1.0 if side == "l" else -1.0
+            mask = (xi < us) if side == "l" else (xi > us)
+            r, u, p = sol[:, mask]
+            assert np.allclose(p / r ** G, p0 / rho0 ** G, rtol=1e-10)
+            assert np.allclose(u + sign * 2 * np.sqrt(G * p / r) / (G - 1), u0 + sign * 2 * c0 / (G - 1), rtol=1e-10)
+
+
+def _oracle_to(pr, t_end):
+    cfg = O.Config(pr.sys, pr.nx, pr.ny, pr.x0, pr.x1, pr.y0, pr.y1, pr.bc_x, pr.bc_y, gamma=G)
+    _, rec = O.run(cfg, pr.U0, 1, cfl=pr.cfl, record=True)
+    n = int(3 * t_end / rec["dt"][0]) + 20
+    _, rec = O.run(cfg, pr.U0, n, cfl=pr.cfl, record=True)
+    t, m = 0.0, 0
+    while t + rec["dt"][m] < t_end:
+        t += rec["dt"][m]
+        m += 1
+    U = O.run(cfg, pr.U0, m, cfl=pr.cfl)
+    return O.run(cfg, U, 1, dt=t_end - t)
+
+
+@pytest.mark.parametrize("name", ["sod", "lax"])
+def test_oracle_approaches_the_exact_solution(name):
+    wl, wr = CASES[name]
+    errs = []
+    for n in (100, 200, 400):
+        pr = W.shock_tube(name, n=n)
+        t_end = pr.meta["t_end"]
+        U = _oracle_to(pr, t_end)[:, 0, :]
+        x = (np.arange(n) + 0.5) / n
+        ref = exact(wl, wr, (x - 0.5) / t_end)
+        rho = U[0]
+        u = U[1] / rho
+        p = (G - 1) * (U[2] - 0.5 * rho * u * u)
+        errs.append([np.mean(np.abs(rho - ref[0])), np.mean(np.abs(u - ref[1])), np.mean(np.abs(p - ref[2]))])
+    errs = np.array(errs)
+    print(name, errs)
+    # discontinuities limit L1 convergence to about first order; the errors must fall at every
+    # refinement and be small at N = 400
+    # (measured: Sod rho 4.9e-3, 2.4e-3, 1.2e-3; Lax rho 1.4e-2, 7.2e-3, 3.5e-3)
+    assert np.all(errs[1:] < 0.8 * errs[:-1]), errs
+    assert np.all(errs[-1] < 0.006), errs
