@@ -80,10 +80,7 @@ __global__ void __launch_bounds__(BLOCK) vjp_kernel(VjpArgs a)
     const size_t ncell = (size_t)a.nx * a.ny;
     const bool periodic = a.bc == 0;
 
-    for (int q = tid; q < NCOEF_ROWS * 8; q += BLOCK) {
-        int r = q / 8, l = q % 8;
-        coef[q] = l < 7 ? (double)COEF[r][l].n / (double)COEF[r][l].d : 0.0;
-    }
+    fill_coef(coef);
 
     // tiles renumbered per XCD (neighbouring tiles share cache lines of the staged rows in one L2)
     const int tile = xcd_tile(blockIdx.x, gridDim.x);

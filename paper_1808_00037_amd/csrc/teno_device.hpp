@@ -794,12 +794,26 @@ template <int SYS, int DIR, int NSEG, bool PACK> constexpr int rec_size()
 }
 
 // Fill the block's coefficient table (rows of Tables 2 and 1, correctly rounded in T).
+// The coefficient rows in the working precision, 8 per row (the eighth 0), divided at compile time
+// (correctly rounded, as a run-time division would be); each block copies them into its LDS.
+template <typename T> struct CoefTable { T v[NCOEF_ROWS * 8]; };
+template <typename T> constexpr CoefTable<T> make_coef_table()
+{
+    CoefTable<T> t{};
+    for (int r = 0; r < NCOEF_ROWS; ++r)
+        for (int l = 0; l < 8; ++l) t.v[r * 8 + l] = l < 7 ? T(COEF[r][l].n) / T(COEF[r][l].d) : T(0);
+    return t;
+}
+__device__ constexpr CoefTable<double> COEF_TAB_F64 = make_coef_table<double>();
+__device__ constexpr CoefTable<float> COEF_TAB_F32 = make_coef_table<float>();
+template <typename T> __device__ __forceinline__ const T *coef_table();
+template <> __device__ __forceinline__ const double *coef_table<double>() { return COEF_TAB_F64.v; }
+template <> __device__ __forceinline__ const float *coef_table<float>() { return COEF_TAB_F32.v; }
+
 template <typename T> __device__ __forceinline__ void fill_coef(T *coef)
 {
-    for (int q = threadIdx.x; q < NCOEF_ROWS * 8; q += BLOCK) {
-        int r = q / 8, l = q % 8;
-        coef[q] = l < 7 ? T(COEF[r][l].n) / T(COEF[r][l].d) : T(0);
-    }
+    const T *tab = coef_table<T>();
+    for (int q = threadIdx.x; q < NCOEF_ROWS * 8; q += BLOCK) coef[q] = tab[q];
 }
 
 // One tile of a sweep: NSEG line segments staged together in LDS. `tile` enumerates the tiles of
