@@ -281,6 +281,33 @@ def random_directions(seed, U0, count):
 # The paper's one-dimensional shock tubes (section "Isolated wave structure") and its shock /
 # entropy-wave cases (Shu-Osher on 200 cells, Titarev-Toro on 400; domain [0, 10]).
 # ------------------------------------------------------------------------------------------------
+def vortex(n, cfl=0.5, strength=5.0, length=10.0):
+    """Isentropic vortex in a uniform stream (rho, u, v, p) = (1, 1, 1, 1) on the periodic
+    [0, length]^2, centred in it: an exact solution of the 2D Euler equations that translates with the
+    stream. Point values at cell centres. (The periodic data take the nearest image of the centre; on
+    [0, 10]^2 the vortex's tail at the seams is of order 1e-5, on [0, 20]^2 below 1e-20.)"""
+    x = cell_centres(0.0, length, n)
+    X, Y = np.meshgrid(x, x)
+    rho, u, v, p = vortex_exact_primitive(X, Y, 0.0, strength, length=length)
+    return Problem("vortex", EULER2D, n, n, 0.0, length, 0.0, length, PERIODIC, PERIODIC,
+                   conserved_2d(rho, u, v, p), cfl=cfl, meta=dict(strength=strength, length=length))
+
+
+def vortex_exact_primitive(X, Y, t, strength=5.0, gamma=GAMMA, length=10.0):
+    """(rho, u, v, p) of the translating vortex at time t (nearest periodic image of the centre)."""
+    h = 0.5 * length
+    xc, yc = h + t, h + t
+    dx = (X - xc + h) % length - h
+    dy = (Y - yc + h) % length - h
+    r2 = dx * dx + dy * dy
+    e1 = np.exp(0.5 * (1.0 - r2))
+    u = 1.0 - strength / (2.0 * math.pi) * e1 * dy
+    v = 1.0 + strength / (2.0 * math.pi) * e1 * dx
+    T = 1.0 - (gamma - 1.0) * strength ** 2 * np.exp(1.0 - r2) / (8.0 * gamma * math.pi ** 2)
+    rho = T ** (1.0 / (gamma - 1.0))
+    return rho, u, v, rho * T
+
+
 def shock_tube(kind, n=200):
     x = cell_centres(0.0, 1.0, n) if kind in ("sod", "lax") else cell_centres(0.0, 10.0, n)
     if kind == "sod":
