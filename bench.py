@@ -9,7 +9,11 @@ resident in HBM before the timed region. The step is captured once in a HIP grap
 
 value = cells * 3 * steps / wall time  (cell-updates per second, one GPU), reported in Gcell-updates/s.
 
-Prints one JSON line (see the repository's design notes for the roofline and baseline fields).
+Prints one JSON line: the throughput; `roofline` for the x-sweep + stage kernel (algorithmic FP64
+flops per launch over its HIP-event launch time, against the FP64 vector peak, with the HBM bytes per
+launch from the committed rocprofv3 counter summary while its kernel-source hash matches); `hbm`;
+per-kernel times; the batched, FP32, TENO5 and adjoint side runs; and `cpu_baseline`, the oracle
+timed on one host core over a bounded strip of the same state.
 """
 import argparse
 import hashlib
