@@ -120,8 +120,7 @@ __global__ void __launch_bounds__(BLOCK) vjp_kernel(VjpArgs a)
             double E = a.U[(size_t)(NV - 1) * ncell + off];
             double sq, rs;
             sqrt_rsqrt(rho, sq, rs);
-            double ir = rs * rs;
-            if (!(rho > 0.0)) ir = 1.0 / rho;
+            double ir = rs * rs;          // (the recorded forward states are physical)
             double un = mn * ir, ut = mt * ir;
             double p = (a.gamma - 1.0) * (E - 0.5 * rho * (un * un + ut * ut));
             r[0] = rho;
