@@ -98,7 +98,16 @@ __global__ void __launch_bounds__(BLOCK) vjp_kernel(VjpArgs a)
     };
 
     // ---- stage the state record, lambda and a zeroed accumulator ----
-    for (int idx = tid; idx < ADJ_NSEG * SEG_LOAD; idx += BLOCK) {
+    // a thread's cells (up to IT of them) are all loaded before any is converted, so that the loads'
+    // latencies overlap
+    constexpr int NCELL = ADJ_NSEG * SEG_LOAD, IT = (NCELL + BLOCK - 1) / BLOCK;
+    double uc[IT][NV], lc[IT][NV];
+    int pos[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int idx = tid + it * BLOCK;
+        pos[it] = -1;
+        if (idx >= NCELL) continue;
         int s, q;
         if (DIR == 0) { s = idx / SEG_LOAD; q = idx % SEG_LOAD; }
         else          { s = idx % ADJ_NSEG; q = idx / ADJ_NSEG; }
@@ -108,16 +117,24 @@ __global__ void __launch_bounds__(BLOCK) vjp_kernel(VjpArgs a)
         const int c = c0 - ADJ_HALO + q;
         const int g = bc_index(c, a.len, a.bc);
         const bool real = periodic || (c >= 0 && c < a.len);
-        size_t off = DIR == 0 ? (size_t)line * a.nx + g : (size_t)g * a.nx + line;
-        double *r = rec + s * STRIDE + q;
+        const size_t off = DIR == 0 ? (size_t)line * a.nx + g : (size_t)g * a.nx + line;
+        pos[it] = s * STRIDE + q;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const size_t fo = (size_t)gvar<SYS, DIR>(v) * ncell + off;
+            uc[it][v] = a.U[fo];
+            lc[it][v] = real ? a.lam[fo] : 0.0;
+        }
+    }
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        if (pos[it] < 0) continue;
+        double *r = rec + pos[it];
         if constexpr (!EULER) {
-            r[0] = a.U[off];
+            r[0] = uc[it][0];
         } else {
             using S = Sys<SYS>;
-            double rho = a.U[off];
-            double mn = a.U[(size_t)gvar<SYS, DIR>(1) * ncell + off];
-            double mt = NV == 4 ? a.U[(size_t)gvar<SYS, DIR>(2) * ncell + off] : 0.0;
-            double E = a.U[(size_t)(NV - 1) * ncell + off];
+            const double rho = uc[it][0], mn = uc[it][1], mt = NV == 4 ? uc[it][2] : 0.0, E = uc[it][NV - 1];
             double sq, rs;
             sqrt_rsqrt(rho, sq, rs);
             double ir = rs * rs;          // (the recorded forward states are physical)
@@ -135,7 +152,7 @@ __global__ void __launch_bounds__(BLOCK) vjp_kernel(VjpArgs a)
         }
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-            r[SEG_LOAD * (LAM + v)] = real ? a.lam[(size_t)gvar<SYS, DIR>(v) * ncell + off] : 0.0;
+            r[SEG_LOAD * (LAM + v)] = lc[it][v];
             r[SEG_LOAD * (ACC + v)] = 0.0;
         }
     }
