@@ -8,7 +8,9 @@ Face arrays: x-faces [.., ny, nx+1] and y-faces [.., ny+1, nx]; face f is the le
 """
 import ctypes
 import os
-from dataclasses import dataclass
+import threading
+from concurrent.futures import ThreadPoolExecutor
+from dataclasses import dataclass, replace
 
 import numpy as np
 
@@ -35,7 +37,8 @@ class _Cfg(ctypes.Structure):
                 ("alpha_mode", ctypes.c_int32), ("pad_", ctypes.c_int32),
                 ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("gamma", ctypes.c_double),
                 ("ct", ctypes.c_double), ("eps_x", ctypes.c_double), ("eps_y", ctypes.c_double),
-                ("adv_speed", ctypes.c_double)]
+                ("adv_speed", ctypes.c_double), ("C", ctypes.c_double), ("q", ctypes.c_int32),
+                ("characteristic", ctypes.c_int32)]
 
 
 @dataclass
@@ -56,14 +59,19 @@ class Config:
     ct: float = 1e-5
     eps: float = None       # None: dx^3 per direction for TENO7X, 1e-40 for TENO5
     adv_speed: float = 1.0
+    C: float = 1.0          # C and q of eq:TENO1 (the paper's values)
+    q: int = 6
+    characteristic: int = 1     # 0: reconstruct per conserved component (L = R = I)
+    dx_: float = None       # cell widths given exactly (windows and strips cut from a larger grid)
+    dy_: float = None
 
     @property
     def dx(self):
-        return (self.x1 - self.x0) / self.nx
+        return self.dx_ if self.dx_ is not None else (self.x1 - self.x0) / self.nx
 
     @property
     def dy(self):
-        return (self.y1 - self.y0) / self.ny
+        return self.dy_ if self.dy_ is not None else (self.y1 - self.y0) / self.ny
 
     @property
     def nvar(self):
@@ -81,7 +89,8 @@ class Config:
         else:
             ex, ey = self.dx ** 3, self.dy ** 3
         return _Cfg(self.sys, self.nx, self.ny, self.bc_x, self.bc_y, self.scheme, self.alpha_mode, 0,
-                    self.dx, self.dy, self.gamma, self.ct, ex, ey, self.adv_speed)
+                    self.dx, self.dy, self.gamma, self.ct, ex, ey, self.adv_speed, self.C, self.q,
+                    self.characteristic)
 
     @property
     def nfaces_x(self):
@@ -111,7 +120,7 @@ def lib():
         L.orc_tables.argtypes = [P, P]
         L.orc_select7.argtypes = [ctypes.c_int]
         L.orc_select7.restype = ctypes.c_int
-        L.orc_flags5_api.argtypes = [P, ctypes.c_double, ctypes.c_double, P, P, P]
+        L.orc_flags5_api.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int32, P, P, P]
         L.orc_recon_api.argtypes = [C, ctypes.c_int, P]
         L.orc_recon_api.restype = ctypes.c_double
         L.orc_table1_api.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, P]
@@ -125,6 +134,7 @@ def lib():
         L.orc_run.argtypes = [C, P, ctypes.c_int, ctypes.c_double, ctypes.c_double, P, P, P]
         L.orc_run_frozen.argtypes = [C, P, ctypes.c_int, P, P, P]
         L.orc_run_frozen_jvp.argtypes = [C, P, P, ctypes.c_int, P, P, P, ctypes.c_double, P]
+        L.orc_rk3_combine.argtypes = [ctypes.c_int, ctypes.c_size_t, P, P, P, ctypes.c_double]
         _lib = L
     return _lib
 
@@ -158,13 +168,13 @@ def select7(pattern):
     return lib().orc_select7(int(pattern))
 
 
-def flags5(f5, eps, ct=1e-5, want_beta=False):
+def flags5(f5, eps, ct=1e-5, want_beta=False, C=1.0, q=6):
     """Cut-off flags (delta0..2) and chi of one five-point stencil given in upwind order."""
     f5 = _f64(f5)
     d = np.zeros(3, dtype=np.int32)
     chi = np.zeros(3)
     beta = np.zeros(3)
-    lib().orc_flags5_api(_p(f5), float(eps), float(ct), _p(d), _p(chi), _p(beta))
+    lib().orc_flags5_api(_p(f5), float(eps), float(ct), float(C), int(q), _p(d), _p(chi), _p(beta))
     if want_beta:
         return d, chi, beta
     return d, chi
@@ -309,3 +319,107 @@ def run_frozen_jvp(cfg, U, d, rec, h=1e-20):
                                   float(h), _p(out))
     _check(st, "run_frozen_jvp")
     return out
+
+
+# ------------------------------------------------------------------------------------------------
+# Drivers for large 2D states: the operator strip by strip in parallel threads, and one SSP-RK3 step
+# stage by stage with every face's selection visible. Both only call the functions above in the
+# order the oracle itself does, and are bitwise equal to rhs() and run() (tests/test_oracle_strips.py).
+# ------------------------------------------------------------------------------------------------
+HALO = 5    # a cell's derivative reads the cells within five of it along its row and column
+
+
+def rk3_combine(stage, U0, Us, dU, dt):
+    """In place: Us (the input of SSP-RK3 stage `stage`) becomes the stage's output, given dU = L(Us)."""
+    for a in (U0, Us, dU):
+        assert a.dtype == np.float64 and a.flags.c_contiguous and a.size == Us.size
+    lib().orc_rk3_combine(int(stage), Us.size, _p(U0), _p(Us), _p(dU), float(dt))
+
+
+def _strip(cfg, U, j0, j1):
+    """Rows j0-HALO .. j1+HALO-1 of U (wrapped or clamped along y) and the matching configuration
+    (outflow along y: the halo rows hold what a wider domain would give the strip's own rows)."""
+    rows = np.arange(j0 - HALO, j1 + HALO)
+    rows = rows % cfg.ny if cfg.bc_y == PERIODIC else np.clip(rows, 0, cfg.ny - 1)
+    nr = len(rows)
+    # (the cell widths, and with them eps = dx^3, dy^3, are the whole grid's exactly)
+    sc = replace(cfg, ny=nr, y0=0.0, y1=1.0, bc_y=OUTFLOW, dx_=cfg.dx, dy_=cfg.dy)
+    return sc, np.ascontiguousarray(U[:, rows, :])
+
+
+def _strip_eval(cfg, U, alpha, j0, j1, want_faces):
+    sc, Us = _strip(cfg, U, j0, j1)
+    r = rhs(sc, Us, alpha=alpha, want_faces=want_faces)
+    n = j1 - j0
+    if not want_faces:
+        return r[:, HALO:HALO + n, :], None
+    d, ex = r
+    fy = n + (1 if j1 == cfg.ny else 0)           # y-faces j0 .. j1-1 (and ny for the last strip)
+    own = dict(masks_x=ex["masks_x"][HALO:HALO + n], flags_x=ex["flags_x"][HALO:HALO + n],
+               chi_x=ex["chi_x"][HALO:HALO + n], Fx=ex["Fx"][:, HALO:HALO + n],
+               masks_y=ex["masks_y"][HALO:HALO + fy], flags_y=ex["flags_y"][HALO:HALO + fy],
+               chi_y=ex["chi_y"][HALO:HALO + fy], Fy=ex["Fy"][:, HALO:HALO + fy], alpha=ex["alpha"])
+    return d[:, HALO:HALO + n, :], own
+
+
+def rhs_strips(cfg, U, alpha, strip_rows=128, threads=1, on_faces=None):
+    """The operator of a 2D Euler state evaluated strip by strip: rows [j0, j1) with HALO rows on
+    either side, with the Lax-Friedrichs constants `alpha` of the whole state given. Bitwise equal to
+    rhs(cfg, U, alpha). Strips run in `threads` threads (the library calls release the GIL).
+    on_faces(j0, j1, faces): called in the calling thread, strip by strip, with the strip's own
+    faces (x-faces of rows j0..j1-1, y-faces j0..j1-1 and, for the last strip, ny): masks, flags,
+    chi, face fluxes."""
+    assert cfg.sys == EULER2D
+    U = _f64(U, cfg.shape)
+    alpha = _f64(alpha)
+    lib()
+    tables()                                   # the coefficient tables set up before any thread
+    out = np.empty(cfg.shape)
+    spans = [(j, min(j + strip_rows, cfg.ny)) for j in range(0, cfg.ny, strip_rows)]
+    want = on_faces is not None
+    with ThreadPoolExecutor(max_workers=max(1, threads)) as ex:
+        pending = []
+        it = iter(spans)
+        window = 2 * max(1, threads)           # results in flight (bounds the memory of face data)
+        for sp in it:
+            pending.append((sp, ex.submit(_strip_eval, cfg, U, alpha, sp[0], sp[1], want)))
+            if len(pending) >= window:
+                (a, b), fut = pending.pop(0)
+                d, faces = fut.result()
+                out[:, a:b] = d
+                if want:
+                    on_faces(a, b, faces)
+        for (a, b), fut in pending:
+            d, faces = fut.result()
+            out[:, a:b] = d
+            if want:
+                on_faces(a, b, faces)
+    return out
+
+
+def step_stages(cfg, U, dt=0.0, cfl=0.5, strip_rows=None, threads=1, on_faces=None):
+    """One SSP-RK3 step, stage by stage: each stage's Lax-Friedrichs constants from its own input
+    (wave_speeds over the whole state), its operator (rhs, or rhs_strips for 2D Euler when
+    strip_rows is given) and rk3_combine; dt > 0 is used as given, else cfl / the CFL denominator of
+    U. on_faces(stage, j0, j1, faces) sees every face of every stage (faces as in rhs_strips; the
+    whole domain at once without strips). Returns (U_new, dict(alpha=[3, 8], dt=dt)); bitwise equal
+    to run(cfg, U, 1, dt, cfl)."""
+    U0 = _f64(U, cfg.shape).copy()
+    if not dt > 0.0:
+        _, den = wave_speeds(cfg, U0)
+        dt = cfl / den
+    Us = U0.copy()
+    alphas = np.zeros((3, 8))
+    for stage in range(3):
+        a, _ = wave_speeds(cfg, Us)
+        alphas[stage] = a
+        if strip_rows is not None:
+            cb = None if on_faces is None else (lambda j0, j1, f, s=stage: on_faces(s, j0, j1, f))
+            dU = rhs_strips(cfg, Us, a, strip_rows=strip_rows, threads=threads, on_faces=cb)
+        elif on_faces is not None:
+            dU, ex = rhs(cfg, Us, alpha=a, want_faces=True)
+            on_faces(stage, 0, cfg.ny, ex)
+        else:
+            dU = rhs(cfg, Us, alpha=a)
+        rk3_combine(stage, U0, Us, np.ascontiguousarray(dU), dt)
+    return Us, dict(alpha=alphas, dt=dt)

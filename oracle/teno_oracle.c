@@ -46,9 +46,7 @@
 
 #define ORC_G 4 /* ghost cells: face i+1/2 reads i-3..i+4 and the flags of its neighbour faces */
 
-/* TENO smoothness-measure constants of eq:TENO1: C = 1, q = 6. */
-#define ORC_C 1.0
-#define ORC_Q 6
+/* The constants C and q of eq:TENO1 are configuration (the paper's values: C = 1, q = 6). */
 
 typedef struct {
     int32_t sys;        /* ORC_ADV1D, ORC_EULER1D, ORC_EULER2D, ORC_BURGERS1D */
@@ -62,6 +60,10 @@ typedef struct {
     double ct;          /* cut-off C_T of eq:seclect */
     double eps_x, eps_y;/* epsilon of eq:TENO1 for x- and y-faces */
     double adv_speed;   /* a in u_t + a u_x = 0 */
+    double C;           /* C of eq:TENO1 (the paper: 1) */
+    int32_t q;          /* q of eq:TENO1 (the paper: 6), q >= 1 */
+    int32_t characteristic; /* 1: reconstruct in characteristic variables (Remark 3); 0: per conserved
+                               component (L = R = I, one Lax-Friedrichs constant max(|u_n| + c)) */
 } orc_cfg;
 
 static int orc_nvar(const orc_cfg *c)
@@ -175,16 +177,16 @@ static void orc_beta5(double a, double b, double c, double d, double e, double b
 }
 
 static void orc_flags5(double a, double b, double c, double d, double e, double eps, double ct,
-                       int delta[3], double chi[3])
+                       double C, int q, int delta[3], double chi[3])
 {
     double beta[3];
     orc_beta5(a, b, c, d, e, beta);
     double tau = fabs(beta[0] - beta[2]);
     double g[3], sum = 0.0;
     for (int k = 0; k < 3; ++k) {
-        double r = ORC_C + tau / (beta[k] + eps);
+        double r = C + tau / (beta[k] + eps);
         double p = 1.0;
-        for (int q = 0; q < ORC_Q; ++q) p *= r;
+        for (int j = 0; j < q; ++j) p *= r;
         g[k] = p;
         sum += g[k];
     }
@@ -255,11 +257,13 @@ int orc_wave_speeds(const orc_cfg *c, const double *U, double *alpha, double *cf
             lx[0] = ux - cs; lx[1] = ux; lx[2] = ux; lx[3] = ux + cs;
             ly[0] = uy - cs; ly[1] = uy; ly[2] = uy; ly[3] = uy + cs;
         } else lx[0] = ux;
+        /* per conserved component, every component needs the largest wave speed */
+        const int scalar = c->alpha_mode || !c->characteristic;
         for (int s = 0; s < nf; ++s) {
-            double ax = c->alpha_mode ? fabs(ux) + cs : fabs(lx[s]);
+            double ax = scalar ? fabs(ux) + cs : fabs(lx[s]);
             if (ax > alpha[s]) alpha[s] = ax;
             if (c->sys == ORC_EULER2D) {
-                double ay = c->alpha_mode ? fabs(uy) + cs : fabs(ly[s]);
+                double ay = scalar ? fabs(uy) + cs : fabs(ly[s]);
                 if (ay > alpha[4 + s]) alpha[4 + s] = ay;
             }
         }
@@ -314,7 +318,7 @@ static int orc_select_all(const orc_cfg *c, const double *U, const double *alpha
                         for (int var = 0; var < nv; ++var) Us[k][var] = P[((size_t)var * py + jp) * px + ip];
                     }
                 }
-                face_eigen_r(c, dir, Us[3], Us[4], L, R, &c2);
+                face_basis_r(c, dir, Us[3], Us[4], L, R, &c2);
                 if (!(c2 > 0.0)) { status = isfinite(c2) ? ORC_E_NONPHYSICAL : ORC_E_NONFINITE; break; }
                 project_r(c, dir, nv, Us, L, alpha, v);
                 uint32_t word = 0;
@@ -322,9 +326,9 @@ static int orc_select_all(const orc_cfg *c, const double *U, const double *alpha
                     int dp[3], dm[3];
                     double xp[3], xm[3];
                     orc_flags5(v[0][s][1], v[0][s][2], v[0][s][3], v[0][s][4], v[0][s][5],
-                               eps, c->ct, dp, xp);
+                               eps, c->ct, c->C, c->q, dp, xp);
                     orc_flags5(v[1][s][6], v[1][s][5], v[1][s][4], v[1][s][3], v[1][s][2],
-                               eps, c->ct, dm, xm);
+                               eps, c->ct, c->C, c->q, dm, xm);
                     for (int k = 0; k < 3; ++k) {
                         word |= (uint32_t)dp[k] << (6 * s + k);
                         word |= (uint32_t)dm[k] << (6 * s + 3 + k);
@@ -394,10 +398,11 @@ int orc_select7(int pattern)
 }
 
 /* Flags of one five-point stencil (upwind order), for tests. */
-void orc_flags5_api(const double *f5, double eps, double ct, int32_t *delta, double *chi, double *beta)
+void orc_flags5_api(const double *f5, double eps, double ct, double C, int32_t q, int32_t *delta, double *chi,
+                    double *beta)
 {
     int d[3];
-    orc_flags5(f5[0], f5[1], f5[2], f5[3], f5[4], eps, ct, d, chi);
+    orc_flags5(f5[0], f5[1], f5[2], f5[3], f5[4], eps, ct, C, q, d, chi);
     orc_beta5(f5[0], f5[1], f5[2], f5[3], f5[4], beta);
     for (int k = 0; k < 3; ++k) delta[k] = d[k];
 }
@@ -450,6 +455,7 @@ int orc_rhs(const orc_cfg *c, const double *U, const double *alpha_in, double *d
     orc_init_tables();
     if (!c || !U || !dUdt || c->nx < 1 || c->ny < 1) return ORC_E_ARG;
     if (c->sys != ORC_EULER2D && c->ny != 1) return ORC_E_ARG;
+    if (c->q < 1 || !(c->C > 0.0)) return ORC_E_ARG;
     double alpha[8], den;
     int st = orc_wave_speeds(c, U, alpha, &den);
     if (st) return st;
@@ -492,6 +498,20 @@ int orc_rhs_frozen_jvp(const orc_cfg *c, const double *U, const double *d, const
     return st;
 }
 
+/* One stage of the Shu-Osher SSP-RK3 step (Gottlieb, Shu & Tadmor 2001; the paper omits the
+ * formula), over n values: Us holds the stage input U^(k) and receives the stage output,
+ *   stage 0: U1 = U0 + dt L(U0);  stage 1: U2 = 3/4 U0 + 1/4 (U1 + dt L(U1));
+ *   stage 2: U3 = 1/3 U0 + 2/3 (U2 + dt L(U2)),
+ * with dU = L(U^(k)) given. */
+void orc_rk3_combine(int stage, size_t n, const double *U0, double *Us, const double *dU, double dt)
+{
+    for (size_t q = 0; q < n; ++q) {
+        if (stage == 0)      Us[q] = U0[q] + dt * dU[q];
+        else if (stage == 1) Us[q] = 0.75 * U0[q] + 0.25 * (Us[q] + dt * dU[q]);
+        else                 Us[q] = (1.0 / 3.0) * U0[q] + (2.0 / 3.0) * (Us[q] + dt * dU[q]);
+    }
+}
+
 /* SSP-RK3 trajectory. dt_fixed > 0: that step size; else dt = cfl / max_j(...) from U^n.
  * Recording (all nullable): masks [nsteps][3][nfaces], alpha [nsteps][3][8], dt [nsteps].
  * Each stage's alpha and selection come from that stage's own input state. */
@@ -525,11 +545,7 @@ int orc_run(const orc_cfg *c, double *U, int nsteps, double dt_fixed, double cfl
             if (st) break;
             if (rec_masks) memcpy(rec_masks + ((size_t)step * 3 + stage) * nf, m, nf * sizeof(uint32_t));
             if (rec_alpha) memcpy(rec_alpha + ((size_t)step * 3 + stage) * 8, a8, sizeof a8);
-            for (size_t q = 0; q < n; ++q) {
-                if (stage == 0)      Us[q] = U0[q] + dt * dU[q];
-                else if (stage == 1) Us[q] = 0.75 * U0[q] + 0.25 * (Us[q] + dt * dU[q]);
-                else                 Us[q] = (1.0 / 3.0) * U0[q] + (2.0 / 3.0) * (Us[q] + dt * dU[q]);
-            }
+            orc_rk3_combine(stage, n, U0, Us, dU, dt);
         }
         if (st == 0) memcpy(U, Us, n * sizeof(double));
     }
