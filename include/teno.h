@@ -64,18 +64,23 @@ typedef struct {
                            1: one constant max_j(|u_n| + c) for all fields */
     int32_t eps_mode;   /* 0: eps = dx^3 per direction for TENO7X (section "The parameter epsilon"),
                            1e-40 for TENO5 (eq:TENO1); 1: the constant `eps` below */
-    int32_t reserved;
+    int32_t q;          /* exponent q of eq:TENO1, 1..12 (the paper: 6) */
     double gamma;       /* ratio of specific heats (1.4) */
-    double ct;          /* cut-off C_T of eq:seclect (1e-5) */
+    double ct;          /* cut-off C_T of eq:seclect, 0 < C_T < 1/3 (the paper: 1e-5) */
     double eps;         /* used when eps_mode = 1 */
     double cfl;         /* CFL number of the time-step rule */
     double adv_speed;   /* a of u_t + a u_x = 0 (TENO_ADV1D) */
+    double C;           /* constant C of eq:TENO1, > 0 (the paper: 1) */
+    int32_t characteristic; /* 1: reconstruct in characteristic variables (Remark 3; the paper);
+                               0: per conserved component (no projection), with the one
+                               Lax-Friedrichs constant max_j(|u_n| + c) for every component */
+    int32_t reserved;   /* 0 */
 } teno_opts;
 
 typedef struct teno_ctx teno_ctx;
 
-/* Fill *o with the paper's parameters: TENO7X, per-field alpha, eps = dx^3, gamma = 1.4,
- * C_T = 1e-5, CFL 0.5, a = 1. */
+/* Fill *o with the paper's parameters: TENO7X, per-field alpha, eps = dx^3, C = 1, q = 6
+ * (eq:TENO1), characteristic-wise reconstruction, gamma = 1.4, C_T = 1e-5, CFL 0.5, a = 1. */
 void teno_default_opts(teno_opts *o);
 
 /* Human-readable name of a status code (static string). */
@@ -87,9 +92,16 @@ const char *teno_status_str(teno_status s);
  * a small output buffer. Errors: TENO_E_ARG (null tflops, iters outside 1..2^24), TENO_E_HIP. */
 teno_status teno_probe_fp64_fma(void *stream, int32_t iters, double *tflops);
 
+/* Device memory, in bytes, that a context for (grid, opts) allocates by itself at most: the control
+ * block (at teno_create), the SSP-RK3 stage scratch (two states, plus the y-part of dU/dt for 2D
+ * Euler; at the first step), and, when ckpt_every > 0, the scratch of a reverse sweep
+ * teno_run_vjp(.., ckpt_every, ..) ((3 ckpt_every + 3) double states). Caller-owned buffers
+ * (states, masks, checkpoints) are not included. Returns 0 for an invalid grid or opts. */
+size_t teno_workspace_bytes(const teno_grid *grid, const teno_opts *opts, int32_t ckpt_every);
+
 /* Create a context for one problem on the current HIP device; `stream` is a hipStream_t (NULL =
- * the null stream). Allocates the context's own device scratch: three state-sized buffers for the
- * RK3 stages and a small control block. Errors: TENO_E_ARG for an invalid grid/opts,
+ * the null stream). Allocates the context's control block now and its RK3 scratch at the first
+ * step (teno_workspace_bytes). Errors: TENO_E_ARG for an invalid grid/opts,
  * TENO_E_HIP if an allocation fails. */
 teno_status teno_create(const teno_grid *grid, const teno_opts *opts, void *stream, teno_ctx **out);
 
@@ -113,10 +125,13 @@ teno_status teno_set_stream(teno_ctx *ctx, void *stream);
 teno_status teno_rhs(teno_ctx *ctx, const void *U, void *dUdt, uint32_t *masks_out);
 
 /* Parity/debug form of teno_rhs: the numerical face fluxes Fx [nvar][ny][nx+1] and (2D)
- * Fy [nvar][ny+1][nx], mask and flag words (each nullable except Fx), and the eight Lax-Friedrichs
+ * Fy [nvar][ny+1][nx], mask and flag words (each nullable except Fx), the normalised smoothness
+ * measures chi_k of eq:norm (chi, nullable: 24 values of the state's element type per face, in
+ * face-word order, value 6s + 3 side + k for field s, side 0 = '+' / 1 = '-', k = 0..2; every face's
+ * chi is evaluated, also where all stencils are provably kept), and the eight Lax-Friedrichs
  * constants used (alpha_dev, nullable: [0..3] x-fields, [4..7] y-fields, double). */
 teno_status teno_face_fluxes(teno_ctx *ctx, const void *U, void *Fx, void *Fy, uint32_t *masks,
-                             uint32_t *flags, double *alpha_dev);
+                             uint32_t *flags, void *chi, double *alpha_dev);
 
 /* The operator with the selection (masks, teno_nfaces() words) and the eight Lax-Friedrichs
  * constants (alpha_dev, double) held fixed instead of computed from U. */
@@ -130,8 +145,17 @@ teno_status teno_rhs_frozen(teno_ctx *ctx, const void *U, const uint32_t *masks,
 teno_status teno_step(teno_ctx *ctx, void *U, double dt_fixed);
 
 /* nsteps calls of teno_step. use_graph = 1 captures one step into a HIP graph on first use and
- * replays it (identical results; fewer launches). */
-teno_status teno_run(teno_ctx *ctx, void *U, int32_t nsteps, double dt_fixed, int32_t use_graph);
+ * replays it (identical results; fewer launches).
+ * check_every <= 0: everything is enqueued without synchronisation; device failures are left to
+ * teno_poll. check_every = k > 0: after every k steps (and after the last) the stream is
+ * synchronised and the device error word read; on a failure no further step is enqueued, the error
+ * word is cleared and TENO_E_NONPHYSICAL / TENO_E_NONFINITE returned. steps_done_host (nullable)
+ * receives the number of steps that completed without a failure: nsteps on success, else the index
+ * of the first step in which one was detected (U then holds the state after the last enqueued
+ * step). Each step's failures are attributed to it by the device as they are raised, so the index
+ * does not depend on k. */
+teno_status teno_run(teno_ctx *ctx, void *U, int32_t nsteps, double dt_fixed, int32_t use_graph,
+                     int32_t check_every, int32_t *steps_done_host);
 
 /* Synchronise the stream and return (then clear) the sticky device error status. */
 teno_status teno_poll(teno_ctx *ctx);
@@ -169,7 +193,8 @@ teno_status teno_read_timing(teno_ctx *ctx, double *ms, int32_t *count);
  * These entry points differentiate the operator and the RK3 trajectory with every stencil
  * selection, every Lax-Friedrichs constant and every dt held at the values of a recorded forward
  * run (the selection is piecewise constant in U, so this is the derivative almost everywhere).
- * Only TENO_F64 contexts support them. */
+ * Only TENO_F64 contexts with characteristic-wise reconstruction support them (TENO_E_UNSUPPORTED
+ * otherwise). */
 
 /* Vector-Jacobian product of the frozen operator at U: grad = (dL/dU)^T lam. Overwrites grad.
  * Periodic directions need at least 8 cells (TENO_E_UNSUPPORTED otherwise). */

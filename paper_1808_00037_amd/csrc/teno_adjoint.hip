@@ -72,7 +72,7 @@ static void enqueue_rhs_vjp(teno_ctx *c, const double *U, const uint32_t *masks,
 
 static bool adjoint_supported(const teno_ctx *c)
 {
-    if (c->grid.dtype != TENO_F64) return false;
+    if (c->grid.dtype != TENO_F64 || !c->opts.characteristic) return false;
     if (c->grid.bc_x == TENO_BC_PERIODIC && c->grid.nx < 8) return false;
     if (c->grid.sys == TENO_EULER2D && c->grid.bc_y == TENO_BC_PERIODIC && c->grid.ny < 8) return false;
     return true;

@@ -26,6 +26,7 @@
 
 #include "teno.h"
 #include "teno_device.hpp"
+#include "teno_internal.hpp"
 
 using namespace teno;
 
@@ -75,6 +76,9 @@ template <typename T> struct BatchSweep {
     T ct, gamma;
     T gm1;                          // gamma - 1, formed in double as the single-problem solver does
     T smooth_k;                     // all-smooth shortcut factor for ct
+    T C;                            // C and q of eq:TENO1
+    int q;
+    int characteristic;             // 0: reconstruction per conserved component
 };
 
 int nseg_of(int len) { return (len + SEG_CELLS - 1) / SEG_CELLS; }
@@ -101,6 +105,7 @@ __device__ __forceinline__ SweepArgs<T> item_args(const BatchSweep<T> &b, const 
     a.addend = (b.addend && SYS == EULER2D) ? b.addend + I.off : nullptr;
     a.out = b.out + I.off;
     a.Fout = nullptr;
+    a.chi_out = nullptr;
     a.masks_out = nullptr;
     a.flags_out = nullptr;
     a.masks_in = nullptr;
@@ -130,6 +135,9 @@ __device__ __forceinline__ SweepArgs<T> item_args(const BatchSweep<T> &b, const 
     a.adv = T(1);
     a.inv_dx = (T)I.inv_dx;
     a.inv_dy = (T)I.inv_dy;
+    a.C = b.C;
+    a.q = b.q;
+    a.characteristic = b.characteristic;
     return a;
 }
 
@@ -272,9 +280,12 @@ BatchSweep<T> base_args(const teno_batch *b)
     a.ictrl = b->ictrl_d;
     a.err = b->err_d;
     a.scheme = b->opts.scheme;
-    a.alpha_mode = b->opts.alpha_mode;
+    a.alpha_mode = teno_alpha_mode(b->opts);
     a.ct = (T)b->opts.ct;
-    a.smooth_k = (T)smooth_shortcut_k(b->opts.ct);
+    a.smooth_k = (T)smooth_shortcut_k(b->opts.ct, b->opts.C, b->opts.q);
+    a.C = (T)b->opts.C;
+    a.q = b->opts.q;
+    a.characteristic = b->opts.characteristic;
     a.gamma = (T)b->opts.gamma;
     a.gm1 = (T)(b->opts.gamma - 1.0);
     return a;
@@ -399,7 +410,7 @@ void enqueue_init(teno_batch *b, hipStream_t s, const T *U, int first, int last)
     int grid = end - beg < 4096 ? end - beg : 4096;
     if (grid > 0)
         hipLaunchKernelGGL((batch_wavespeed_kernel<T>), dim3(grid), dim3(BLOCK), 0, s, U, b->inst_d, b->ictrl_d,
-                           b->items_w_d, beg, end, (T)b->opts.gamma, b->opts.alpha_mode, 0, b->err_d);
+                           b->items_w_d, beg, end, (T)b->opts.gamma, teno_alpha_mode(b->opts), 0, b->err_d);
 }
 
 template <typename T>
@@ -508,9 +519,7 @@ teno_status teno_batch_create(const teno_grid *grids, int32_t n, const teno_opts
         if (g.bc_x < 0 || g.bc_x > 1 || g.bc_y < 0 || g.bc_y > 1) return TENO_E_ARG;
         if (!(g.x1 > g.x0) || !(g.y1 > g.y0)) return TENO_E_ARG;
     }
-    if (opts->scheme < 0 || opts->scheme > 1 || opts->alpha_mode < 0 || opts->alpha_mode > 1) return TENO_E_ARG;
-    if (!(opts->gamma > 1.0) || !(opts->ct > 0.0 && opts->ct < 1.0 / 3.0) || !(opts->cfl > 0.0)) return TENO_E_ARG;
-    if (opts->eps_mode == 1 && !(opts->eps > 0.0)) return TENO_E_ARG;
+    if (!teno_validate_opts(opts)) return TENO_E_ARG;
 
     teno_batch *b = new (std::nothrow) teno_batch();
     if (!b) return TENO_E_HIP;
@@ -540,7 +549,7 @@ teno_status teno_batch_create(const teno_grid *grids, int32_t n, const teno_opts
         if (opts->eps_mode == 1) eps_x = eps_y = opts->eps;
         else if (opts->scheme == TENO_SCHEME_TENO5) eps_x = eps_y = 1e-40;
         else { eps_x = dx * dx * dx; eps_y = dy * dy * dy; }
-        const double sk = smooth_shortcut_k(opts->ct);
+        const double sk = smooth_shortcut_k(opts->ct, opts->C, opts->q);
         I.eps4_x = 4.0 * eps_x;
         I.eps4_y = 4.0 * eps_y;
         I.keps4_x = sk * I.eps4_x;

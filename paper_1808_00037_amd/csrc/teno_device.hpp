@@ -87,6 +87,8 @@ struct Ctrl {
     double t_end;                              // end time of the runs (used when end_on)
     unsigned err;
     unsigned end_on;                           // steps are cut at t_end, and stand still there
+    unsigned steps;                            // steps begun since the counters were reset
+    unsigned err_at;                           // 1 + index of the step a failure was first seen in (0: none)
 };
 
 // ------------------------------------------------------------------------------------------------
@@ -393,13 +395,15 @@ __device__ __forceinline__ bool all_smooth(const Smooth<T> &m, T k, T keps4)
     return m.tau <= fma(k, bmin, keps4);
 }
 
-// Largest K of the shortcut for cut-off ct: 1 / (1 + 2 (1 + K)^6) >= ct must hold with room for
-// rounding; taken 1% below the bound and capped at 5.
-inline double smooth_shortcut_k(double ct)
+// Largest K of the shortcut for cut-off ct and the constants C, q of eq:TENO1: with
+// tau5 <= K (beta_min + eps) every r_k lies in [C, C + K], so chi_min >= 1 / (1 + 2 (1 + K/C)^q), which
+// must stay >= ct with room for rounding; K is taken 1% below the bound and capped at 5 C
+// (C = 1, q = 6, ct = 1e-5: K = 5).
+inline double smooth_shortcut_k(double ct, double C, int q)
 {
-    double kmax = pow((1.0 / ct - 1.0) * 0.5, 1.0 / 6.0) - 1.0;
+    double kmax = C * (pow((1.0 / ct - 1.0) * 0.5, 1.0 / q) - 1.0);
     double k = 0.99 * kmax;
-    return k < 0.0 ? 0.0 : (k > 5.0 ? 5.0 : k);
+    return k < 0.0 ? 0.0 : (k > 5.0 * C ? 5.0 * C : k);
 }
 
 // Reciprocal from the hardware estimate and two Newton steps (argument normal and positive).
@@ -443,34 +447,62 @@ template <typename T> __device__ __forceinline__ T fast_sqrt(T x)
     return s;
 }
 
-__device__ __forceinline__ unsigned cutoff3(const Smooth<double> &m, double eps4, double ct)
+// r^q for the exponent q of eq:TENO1: ((r r) r)^2 for the paper's q = 6, else q - 1 products.
+template <typename T> __device__ __forceinline__ T pow_q(T r, int q)
+{
+    if (q == 6) {
+        T g = r * r * r;
+        return g * g;
+    }
+    T g = r;
+    for (int j = 1; j < q; ++j) g *= r;
+    return g;
+}
+
+// gamma_k = (C + tau5 / (beta_k + eps))^q of the three substencils, up to one common positive factor
+// (the cut-off and chi only use their ratios).
+__device__ __forceinline__ void gamma3(const Smooth<double> &m, double eps4, double C, int q, double g[3])
 {
     double D0 = m.b0 + eps4, D1 = m.b1 + eps4, D2 = m.b2 + eps4;
     double D01 = D0 * D1;
     double tinv = m.tau * recip(D01 * D2);
-    double r0 = 1.0 + tinv * (D1 * D2);
-    double r1 = 1.0 + tinv * (D0 * D2);
-    double r2 = 1.0 + tinv * D01;
-    double g0 = r0 * r0 * r0, g1 = r1 * r1 * r1, g2 = r2 * r2 * r2;
-    g0 *= g0;
-    g1 *= g1;
-    g2 *= g2;
-    double thr = ct * ((g0 + g1) + g2);
-    return (g0 < thr ? 0u : 1u) | (g1 < thr ? 0u : 2u) | (g2 < thr ? 0u : 4u);
+    double r0 = C + tinv * (D1 * D2);
+    double r1 = C + tinv * (D0 * D2);
+    double r2 = C + tinv * D01;
+    g[0] = pow_q(r0, q);
+    g[1] = pow_q(r1, q);
+    g[2] = pow_q(r2, q);
 }
 
-// Single precision: gamma_k / gamma_max keeps every term in [0, 1] (no overflow of r^6).
-__device__ __forceinline__ unsigned cutoff3(const Smooth<float> &m, float eps4, float ct)
+// Single precision: gamma_k / gamma_max keeps every term in [0, 1] (no overflow of r^q).
+__device__ __forceinline__ void gamma3(const Smooth<float> &m, float eps4, float C, int q, float g[3])
 {
-    float r0 = 1.0f + m.tau / (m.b0 + eps4), r1 = 1.0f + m.tau / (m.b1 + eps4), r2 = 1.0f + m.tau / (m.b2 + eps4);
+    float r0 = C + m.tau / (m.b0 + eps4), r1 = C + m.tau / (m.b1 + eps4), r2 = C + m.tau / (m.b2 + eps4);
     float rm = fmaxf(r0, fmaxf(r1, r2));
-    float q0 = r0 / rm, q1 = r1 / rm, q2 = r2 / rm;
-    float g0 = q0 * q0 * q0, g1 = q1 * q1 * q1, g2 = q2 * q2 * q2;
-    g0 *= g0;
-    g1 *= g1;
-    g2 *= g2;
-    float thr = ct * ((g0 + g1) + g2);
-    return (g0 < thr ? 0u : 1u) | (g1 < thr ? 0u : 2u) | (g2 < thr ? 0u : 4u);
+    g[0] = pow_q(r0 / rm, q);
+    g[1] = pow_q(r1 / rm, q);
+    g[2] = pow_q(r2 / rm, q);
+}
+
+template <typename T>
+__device__ __forceinline__ unsigned cutoff3(const Smooth<T> &m, T eps4, T ct, T C, int q)
+{
+    T g[3];
+    gamma3(m, eps4, C, q, g);
+    T thr = ct * ((g[0] + g[1]) + g[2]);
+    return (g[0] < thr ? 0u : 1u) | (g[1] < thr ? 0u : 2u) | (g[2] < thr ? 0u : 4u);
+}
+
+// chi_k of eq:norm from the same gamma_k.
+template <typename T>
+__device__ __forceinline__ void chi3(const Smooth<T> &m, T eps4, T C, int q, T chi[3])
+{
+    T g[3];
+    gamma3(m, eps4, C, q, g);
+    const T s = (g[0] + g[1]) + g[2];
+    chi[0] = g[0] / s;
+    chi[1] = g[1] / s;
+    chi[2] = g[2] / s;
 }
 
 // Roe-averaged quantities of one face and the rows/columns of its eigenvector matrices.
@@ -484,14 +516,23 @@ template <typename T> struct Roe {
 // LS scales the row by LS (a power of two, so the scaled row is exactly LS times the plain one);
 // the sweeps take LS = 1/2, the half of the flux splitting, folded into each row's own constants.
 // Scalar systems: L = LS, R = 1.
+// characteristic = false: the reconstruction runs per conserved component; field s is the conserved
+// variable s (global order), which is local component `comp` of the sweep: L = LS e_comp, R = e_comp.
 template <typename T, int NV, int LSINV = 1>
-__device__ __forceinline__ void char_basis(const Roe<T> &r, int s, T L[NV], T R[NV])
+__device__ __forceinline__ void char_basis(const Roe<T> &r, int s, T L[NV], T R[NV], bool characteristic = true,
+                                           int comp = 0)
 {
     static_assert(LSINV == 1 || LSINV == 2, "row scale 1 or 1/2");
     constexpr T LS = T(1) / T(LSINV);
     if constexpr (NV == 1) {
         L[0] = LS;
         R[0] = T(1);
+    } else if (!characteristic) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            L[v] = v == comp ? LS : T(0);
+            R[v] = v == comp ? T(1) : T(0);
+        }
     } else {
         const T h = T(0.5) * LS;
         // map the 1D fields (0, 1, 2) onto the 2D ones (0, 1, 3)
@@ -571,6 +612,7 @@ template <typename T> struct SweepArgs {
     const T *addend;            // nullable: dU of the other direction, added per cell
     T *out;                     // MODE_RHS: dU/dt; MODE_STAGE: next stage state
     T *Fout;                    // MODE_FACES: face fluxes
+    T *chi_out;                 // MODE_FACES, nullable: chi of eq:norm, 24 per face (this direction's section)
     uint32_t *masks_out;        // nullable: face mask words (this direction's section)
     uint32_t *flags_out;        // nullable: face flag words (this direction's section)
     const uint32_t *masks_in;   // FROZEN kernels: mask words (this direction's section)
@@ -591,6 +633,9 @@ template <typename T> struct SweepArgs {
     T keps4;                    // smooth_k * eps4
     T gm1;                      // gamma - 1
     T inv_dx, inv_dy;           // for the CFL denominator of the produced state
+    T C;                        // C of eq:TENO1
+    int q;                      // q of eq:TENO1
+    int characteristic;         // 0: reconstruction per conserved component
 };
 
 // Wave speeds of one cell for the GLF constants and the CFL rule.
@@ -620,8 +665,11 @@ __device__ __forceinline__ bool cell_speeds(const T *u, T gamma, T adv, T inv_dx
         T cs = sqrt(gamma * p * ir);
         double c = (double)cs, ux = (double)vx, uy = (double)vy;
         if (alpha_mode) {
-            w[0] = w[1] = w[2] = w[3] = fabs(ux) + c;
-            if (NV == 4) w[4] = w[5] = w[6] = w[7] = fabs(uy) + c;
+            w[0] = w[1] = w[2] = fabs(ux) + c;      // (one-dimensional Euler has three fields)
+            if (NV == 4) {
+                w[3] = w[0];
+                w[4] = w[5] = w[6] = w[7] = fabs(uy) + c;
+            }
         } else if (NV == 3) {
             w[0] = fabs(ux - c); w[1] = fabs(ux); w[2] = fabs(ux + c);
         } else {
@@ -1160,10 +1208,11 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
                 // of the loop (registers held across it) nor needs copies to keep them in place
                 asm volatile("" : "+v"(roe.un), "+v"(roe.ut), "+v"(roe.cs), "+v"(roe.ic), "+v"(roe.H), "+v"(roe.q2),
                                   "+v"(roe.b1), "+v"(roe.b2));
-                char_basis<T, NV, 2>(roe, sf, Ls, Rs);       // L/2: the 1/2 of the splitting
+                // (L/2: the 1/2 of the splitting)
+                char_basis<T, NV, 2>(roe, sf, Ls, Rs, a.characteristic != 0, gvar<SYS, DIR>(sf));
             }
             T vp[8], vm[8];
-            if (NV == 4 && sf == 2) {
+            if (NV == 4 && sf == 2 && a.characteristic) {
                 // shear field: L_2 = (-u_t, 0, 1, 0), so L_2 U = m_t - u_t rho and L_2 F = u_n L_2 U
 #pragma unroll
                 for (int j = 0; j < 8; ++j) {
@@ -1201,6 +1250,19 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
             } else {
                 Smooth<T> sp = smooth5(vp[1], vp[2], vp[3], vp[4], vp[5]);
                 Smooth<T> sm = smooth5(vm[6], vm[5], vm[4], vm[3], vm[2]);
+                if constexpr (MODE == MODE_FACES) {
+                    if (a.chi_out && face_ok) {
+                        T cp[3], cm[3];
+                        chi3(sp, a.eps4, a.C, a.q, cp);
+                        chi3(sm, a.eps4, a.C, a.q, cm);
+                        T *o = a.chi_out + face_index(f) * 24 + 6 * sf;
+#pragma unroll
+                        for (int j = 0; j < 3; ++j) {
+                            o[j] = cp[j];
+                            o[3 + j] = cm[j];
+                        }
+                    }
+                }
                 // (lanes of a packed wave that no piece needs count as smooth: their stencils straddle
                 // two lines)
                 // (both sides evaluated, without a branch between them)
@@ -1215,8 +1277,8 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
                         mp = mm = TENO5_ROW[7];
                     }
                 } else {
-                    unsigned dp = easy ? 7u : cutoff3(sp, a.eps4, a.ct);
-                    unsigned dm = easy ? 7u : cutoff3(sm, a.eps4, a.ct);
+                    unsigned dp = easy ? 7u : cutoff3(sp, a.eps4, a.ct, a.C, a.q);
+                    unsigned dm = easy ? 7u : cutoff3(sm, a.eps4, a.ct, a.C, a.q);
                     unsigned bits = dp | (dm << 3);
                     fword |= bits << (6 * sf);
                     if (a.scheme == 0) {
@@ -1578,6 +1640,10 @@ static __global__ void prep_kernel(Ctrl *ctrl, int ring, int stage, double dt_fi
     }
     if (t == 8) {
         ctrl->den = vals[8];
+        // a failure raised since the last preparation belongs to the step in progress (before the
+        // first step: to the first step)
+        if (ctrl->err && !ctrl->err_at) ctrl->err_at = stage == 0 ? (ctrl->steps ? ctrl->steps : 1u) : ctrl->steps;
+        if (stage == 0) ctrl->steps += 1;
         if (stage == 0) {
             double dt = dt_fixed > 0.0 ? dt_fixed : cfl / vals[8];
             double tn = ctrl->t + dt;
@@ -1595,7 +1661,10 @@ static __global__ void prep_kernel(Ctrl *ctrl, int ring, int stage, double dt_fi
                     at_end = true;
                 }
             }
-            if (!(dt > 0.0 || (at_end && dt == 0.0)) || !isfinite(dt)) atomicOr(&ctrl->err, ERR_NONFINITE);
+            if (!(dt > 0.0 || (at_end && dt == 0.0)) || !isfinite(dt)) {
+                atomicOr(&ctrl->err, ERR_NONFINITE);
+                if (!ctrl->err_at) ctrl->err_at = ctrl->steps;
+            }
             ctrl->dt = dt;
             ctrl->t = tn;
             if (record) record[24] = dt;
@@ -1615,6 +1684,15 @@ static __global__ void set_time_kernel(Ctrl *ctrl, double t0, double t_end, unsi
         ctrl->t = t0;
         ctrl->t_end = t_end;
         ctrl->end_on = on;
+    }
+}
+
+// Start counting steps and attributing failures to them from here (the error word is kept).
+static __global__ void reset_counters_kernel(Ctrl *ctrl)
+{
+    if (threadIdx.x == 0) {
+        ctrl->steps = 0;
+        ctrl->err_at = 0;
     }
 }
 

@@ -40,7 +40,7 @@ struct SweepReq {
     int stage;
     bool frozen;
     const void *U, *U0, *addend;
-    void *out, *Fout;
+    void *out, *Fout, *chi_out;
     uint32_t *masks_out, *flags_out;
     const uint32_t *masks_in;
     const double *alpha;
@@ -48,6 +48,10 @@ struct SweepReq {
 };
 
 bool teno_validate(const teno_grid *g, const teno_opts *o);
+bool teno_validate_opts(const teno_opts *o);
+// The Lax-Friedrichs constants' form: one constant max(|u_n| + c) for every field when asked for,
+// and always for the reconstruction per conserved component (every component needs the fastest wave).
+inline int teno_alpha_mode(const teno_opts &o) { return (o.alpha_mode || !o.characteristic) ? 1 : 0; }
 void teno_fill_derived(teno_ctx *c);
 teno_status teno_ensure_scratch(teno_ctx *c);
 void teno_launch_sweep(teno_ctx *c, const SweepReq &r);

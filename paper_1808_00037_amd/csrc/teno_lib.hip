@@ -50,10 +50,18 @@ bool teno_validate(const teno_grid *g, const teno_opts *o)
     if (g->bc_x < 0 || g->bc_x > 1 || g->bc_y < 0 || g->bc_y > 1) return false;
     if (g->dtype != TENO_F64 && g->dtype != TENO_F32) return false;
     if (!(g->x1 > g->x0) || !(g->y1 > g->y0)) return false;
+    return teno_validate_opts(o);
+}
+
+bool teno_validate_opts(const teno_opts *o)
+{
+    if (!o) return false;
     if (o->scheme < 0 || o->scheme > 1 || o->alpha_mode < 0 || o->alpha_mode > 1) return false;
     if (o->eps_mode < 0 || o->eps_mode > 1) return false;
     if (!(o->gamma > 1.0) || !(o->ct > 0.0 && o->ct < 1.0 / 3.0) || !(o->cfl > 0.0)) return false;
     if (o->eps_mode == 1 && !(o->eps > 0.0)) return false;
+    if (o->q < 1 || o->q > 12 || !(o->C > 0.0) || !std::isfinite(o->C)) return false;
+    if (o->characteristic < 0 || o->characteristic > 1) return false;
     return true;
 }
 
@@ -110,6 +118,7 @@ static void launch_sweep_t(teno_ctx *c, const SweepReq &r)
     a.addend = (const T *)r.addend;
     a.out = (T *)r.out;
     a.Fout = (T *)r.Fout;
+    a.chi_out = (T *)r.chi_out;
     a.masks_out = r.masks_out;
     a.flags_out = r.flags_out;
     a.masks_in = r.masks_in;
@@ -126,9 +135,12 @@ static void launch_sweep_t(teno_ctx *c, const SweepReq &r)
     a.mode = r.mode;
     a.stage = r.stage;
     a.scheme = c->opts.scheme;
-    a.alpha_mode = c->opts.alpha_mode;
+    a.alpha_mode = teno_alpha_mode(c->opts);
+    a.C = (T)c->opts.C;
+    a.q = c->opts.q;
+    a.characteristic = c->opts.characteristic;
     a.inv_h = (T)(1.0 / (DIR == 0 ? c->dx : c->dy));
-    const double eps = DIR == 0 ? c->eps_x : c->eps_y, sk = smooth_shortcut_k(c->opts.ct);
+    const double eps = DIR == 0 ? c->eps_x : c->eps_y, sk = smooth_shortcut_k(c->opts.ct, c->opts.C, c->opts.q);
     a.ct = (T)c->opts.ct;
     a.eps4 = (T)(4.0 * eps);
     a.smooth_k = (T)sk;
@@ -203,19 +215,19 @@ static void launch_wavespeed_t(teno_ctx *c, const void *U, int ring)
     switch (c->grid.sys) {
     case TENO_ADV1D:
         hipLaunchKernelGGL((wavespeed_kernel<T, ADV1D>), dim3(grid), dim3(BLOCK), 0, c->stream, u, c->ncell, g, adv,
-                           ix, iy, c->opts.alpha_mode, part, &c->ctrl_d->err);
+                           ix, iy, teno_alpha_mode(c->opts), part, &c->ctrl_d->err);
         break;
     case TENO_BURGERS1D:
         hipLaunchKernelGGL((wavespeed_kernel<T, BURGERS1D>), dim3(grid), dim3(BLOCK), 0, c->stream, u, c->ncell, g,
-                           adv, ix, iy, c->opts.alpha_mode, part, &c->ctrl_d->err);
+                           adv, ix, iy, teno_alpha_mode(c->opts), part, &c->ctrl_d->err);
         break;
     case TENO_EULER1D:
         hipLaunchKernelGGL((wavespeed_kernel<T, EULER1D>), dim3(grid), dim3(BLOCK), 0, c->stream, u, c->ncell, g,
-                           adv, ix, iy, c->opts.alpha_mode, part, &c->ctrl_d->err);
+                           adv, ix, iy, teno_alpha_mode(c->opts), part, &c->ctrl_d->err);
         break;
     default:
         hipLaunchKernelGGL((wavespeed_kernel<T, EULER2D>), dim3(grid), dim3(BLOCK), 0, c->stream, u, c->ncell, g,
-                           adv, ix, iy, c->opts.alpha_mode, part, &c->ctrl_d->err);
+                           adv, ix, iy, teno_alpha_mode(c->opts), part, &c->ctrl_d->err);
         break;
     }
 }
@@ -355,6 +367,10 @@ void teno_default_opts(teno_opts *o)
     o->eps = 0.0;
     o->cfl = 0.5;
     o->adv_speed = 1.0;
+    o->C = 1.0;
+    o->q = 6;
+    o->characteristic = 1;
+    o->reserved = 0;
 }
 
 const char *teno_status_str(teno_status s)
@@ -422,6 +438,19 @@ teno_status teno_destroy(teno_ctx *c)
     return TENO_OK;
 }
 
+size_t teno_workspace_bytes(const teno_grid *grid, const teno_opts *opts, int32_t ckpt_every)
+{
+    if (!teno_validate(grid, opts) || ckpt_every < 0) return 0;
+    teno_ctx c;
+    c.grid = *grid;
+    c.opts = *opts;
+    teno_fill_derived(&c);
+    const size_t state = c.nelem * c.esize;
+    size_t bytes = sizeof(Ctrl) + 2 * state + (grid->sys == TENO_EULER2D ? state : 0);
+    if (ckpt_every > 0) bytes += ((size_t)3 * (size_t)ckpt_every + 3) * c.nelem * sizeof(double);
+    return bytes;
+}
+
 size_t teno_state_elems(const teno_ctx *c) { return c ? c->nelem : 0; }
 size_t teno_nfaces(const teno_ctx *c) { return c ? c->nfx + c->nfy : 0; }
 
@@ -456,7 +485,7 @@ teno_status teno_rhs_frozen(teno_ctx *c, const void *U, const uint32_t *masks, c
 }
 
 teno_status teno_face_fluxes(teno_ctx *c, const void *U, void *Fx, void *Fy, uint32_t *masks, uint32_t *flags,
-                             double *alpha_dev)
+                             void *chi, double *alpha_dev)
 {
     if (!c || !U || !Fx) return TENO_E_ARG;
     const bool two_d = c->grid.sys == TENO_EULER2D;
@@ -468,12 +497,14 @@ teno_status teno_face_fluxes(teno_ctx *c, const void *U, void *Fx, void *Fy, uin
     r.U = U;
     r.dir = 0;
     r.Fout = Fx;
+    r.chi_out = chi;
     r.masks_out = masks;
     r.flags_out = flags;
     teno_launch_sweep(c, r);
     if (two_d) {
         r.dir = 1;
         r.Fout = Fy;
+        r.chi_out = chi ? (char *)chi + c->nfx * 24 * c->esize : nullptr;
         r.masks_out = masks ? masks + c->nfx : nullptr;
         r.flags_out = flags ? flags + c->nfx : nullptr;
         teno_launch_sweep(c, r);
@@ -493,17 +524,9 @@ teno_status teno_step(teno_ctx *c, void *U, double dt_fixed)
     return hipGetLastError() == hipSuccess ? TENO_OK : TENO_E_HIP;
 }
 
-teno_status teno_run(teno_ctx *c, void *U, int32_t nsteps, double dt_fixed, int32_t use_graph)
+// Make sure the one-step graph for (U, dt_fixed) exists.
+static teno_status ensure_step_graph(teno_ctx *c, void *U, double dt_fixed)
 {
-    if (!c || !U || nsteps < 0) return TENO_E_ARG;
-    teno_status st = teno_ensure_scratch(c);
-    if (st) return st;
-    teno_launch_clear(c, 0);
-    teno_launch_wavespeed(c, U, 0);
-    if (!use_graph) {
-        for (int n = 0; n < nsteps; ++n) teno_enqueue_step(c, U, dt_fixed, nullptr, nullptr, nullptr, nullptr, nullptr);
-        return hipGetLastError() == hipSuccess ? TENO_OK : TENO_E_HIP;
-    }
     if (!c->graph_exec || c->graph_U != U || c->graph_dt != dt_fixed) {
         if (c->graph_exec) hipGraphExecDestroy(c->graph_exec);
         if (c->graph) hipGraphDestroy(c->graph);
@@ -525,7 +548,60 @@ teno_status teno_run(teno_ctx *c, void *U, int32_t nsteps, double dt_fixed, int3
         c->graph_U = U;
         c->graph_dt = dt_fixed;
     }
-    for (int n = 0; n < nsteps; ++n) HIP_TRY(hipGraphLaunch(c->graph_exec, c->stream));
+    return TENO_OK;
+}
+
+// Synchronise, read the error word and the failing step; clear both on a failure.
+static teno_status read_failure(teno_ctx *c, unsigned *err_at)
+{
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    unsigned w[2] = {0, 0};
+    HIP_TRY(hipMemcpy(&w[0], &c->ctrl_d->err, sizeof(unsigned), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(&w[1], &c->ctrl_d->err_at, sizeof(unsigned), hipMemcpyDeviceToHost));
+    unsigned steps = 0;
+    HIP_TRY(hipMemcpy(&steps, &c->ctrl_d->steps, sizeof(unsigned), hipMemcpyDeviceToHost));
+    if (w[0]) {
+        // raised by the last stage of the last step and not yet seen by a stage preparation
+        *err_at = w[1] ? w[1] : (steps ? steps : 1u);
+        const unsigned z[2] = {0, 0};
+        HIP_TRY(hipMemcpy(&c->ctrl_d->err, &z[0], sizeof(unsigned), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(&c->ctrl_d->err_at, &z[1], sizeof(unsigned), hipMemcpyHostToDevice));
+    }
+    return err_to_status(w[0]);
+}
+
+teno_status teno_run(teno_ctx *c, void *U, int32_t nsteps, double dt_fixed, int32_t use_graph, int32_t check_every,
+                     int32_t *steps_done_host)
+{
+    if (!c || !U || nsteps < 0) return TENO_E_ARG;
+    if (steps_done_host) *steps_done_host = 0;
+    teno_status st = teno_ensure_scratch(c);
+    if (st) return st;
+    if (use_graph) {
+        st = ensure_step_graph(c, U, dt_fixed);
+        if (st) return st;
+    }
+    if (check_every > 0) hipLaunchKernelGGL(reset_counters_kernel, dim3(1), dim3(64), 0, c->stream, c->ctrl_d);
+    teno_launch_clear(c, 0);
+    teno_launch_wavespeed(c, U, 0);
+    const int chunk = check_every > 0 ? check_every : (nsteps > 0 ? nsteps : 1);
+    for (int n0 = 0; n0 < nsteps; n0 += chunk) {
+        const int n1 = n0 + chunk < nsteps ? n0 + chunk : nsteps;
+        for (int n = n0; n < n1; ++n) {
+            if (use_graph) HIP_TRY(hipGraphLaunch(c->graph_exec, c->stream));
+            else teno_enqueue_step(c, U, dt_fixed, nullptr, nullptr, nullptr, nullptr, nullptr);
+        }
+        if (hipGetLastError() != hipSuccess) return TENO_E_HIP;
+        if (check_every > 0) {
+            unsigned at = 0;
+            st = read_failure(c, &at);
+            if (st) {
+                if (steps_done_host) *steps_done_host = (int32_t)at - 1;
+                return st;
+            }
+        }
+    }
+    if (steps_done_host) *steps_done_host = nsteps;
     return TENO_OK;
 }
 
@@ -538,6 +614,7 @@ teno_status teno_poll(teno_ctx *c)
     if (e) {
         unsigned z = 0;
         HIP_TRY(hipMemcpy(&c->ctrl_d->err, &z, sizeof z, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(&c->ctrl_d->err_at, &z, sizeof z, hipMemcpyHostToDevice));
     }
     return err_to_status(e);
 }

@@ -40,8 +40,9 @@ class Grid(ctypes.Structure):
 
 class Opts(ctypes.Structure):
     _fields_ = [("scheme", ctypes.c_int32), ("alpha_mode", ctypes.c_int32), ("eps_mode", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("gamma", ctypes.c_double), ("ct", ctypes.c_double),
-                ("eps", ctypes.c_double), ("cfl", ctypes.c_double), ("adv_speed", ctypes.c_double)]
+                ("q", ctypes.c_int32), ("gamma", ctypes.c_double), ("ct", ctypes.c_double),
+                ("eps", ctypes.c_double), ("cfl", ctypes.c_double), ("adv_speed", ctypes.c_double),
+                ("C", ctypes.c_double), ("characteristic", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 _lib = None
@@ -57,10 +58,12 @@ _SIGS = {
     "teno_nfaces": (ctypes.c_size_t, [_P]),
     "teno_set_stream": (ctypes.c_int, [_P, _P]),
     "teno_rhs": (ctypes.c_int, [_P, _P, _P, _P]),
-    "teno_face_fluxes": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P]),
+    "teno_face_fluxes": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P]),
+    "teno_workspace_bytes": (ctypes.c_size_t, [_P, _P, ctypes.c_int32]),
     "teno_rhs_frozen": (ctypes.c_int, [_P, _P, _P, _P, _P]),
     "teno_step": (ctypes.c_int, [_P, _P, ctypes.c_double]),
-    "teno_run": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.c_double, ctypes.c_int32]),
+    "teno_run": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
+                                ctypes.POINTER(ctypes.c_int32)]),
     "teno_poll": (ctypes.c_int, [_P]),
     "teno_last_dt": (ctypes.c_int, [_P, _P]),
     "teno_set_time": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_double]),
@@ -130,20 +133,36 @@ def default_opts():
     return o
 
 
+def make_opts(scheme=TENO7X, alpha_mode=0, eps=None, gamma=1.4, ct=1e-5, cfl=0.5, adv_speed=1.0, C=1.0, q=6,
+              characteristic=1):
+    """teno_opts from the paper's defaults with the given changes (eps None: dx^3 / 1e-40 by scheme)."""
+    o = default_opts()
+    o.scheme, o.alpha_mode, o.gamma, o.ct, o.cfl, o.adv_speed = scheme, alpha_mode, gamma, ct, cfl, adv_speed
+    o.C, o.q, o.characteristic = float(C), int(q), int(characteristic)
+    if eps is not None:
+        o.eps_mode, o.eps = 1, float(eps)
+    return o
+
+
+def workspace_bytes(sys, nx, ny=1, dtype=torch.float64, ckpt_every=0, **opts):
+    """Device bytes a context allocates by itself (teno_workspace_bytes); 0 for invalid arguments."""
+    g = Grid(sys, nx, ny, PERIODIC, PERIODIC, F64 if dtype == torch.float64 else F32, 0.0, 1.0, 0.0, 1.0)
+    o = make_opts(**opts)
+    return lib().teno_workspace_bytes(ctypes.byref(g), ctypes.byref(o), int(ckpt_every))
+
+
 class Solver:
     """One problem instance on the current GPU: grid, boundary conditions and scheme options."""
 
     def __init__(self, sys, nx, ny=1, x0=0.0, x1=1.0, y0=0.0, y1=1.0, bc_x=PERIODIC, bc_y=PERIODIC,
                  dtype=torch.float64, scheme=TENO7X, alpha_mode=0, eps=None, gamma=1.4, ct=1e-5,
-                 cfl=0.5, adv_speed=1.0):
+                 cfl=0.5, adv_speed=1.0, C=1.0, q=6, characteristic=1):
         self.sys, self.nx, self.ny = sys, nx, ny
         self.dtype = dtype
         self.nvar = NVAR[sys]
         g = Grid(sys, nx, ny, bc_x, bc_y, F64 if dtype == torch.float64 else F32, x0, x1, y0, y1)
-        o = default_opts()
-        o.scheme, o.alpha_mode, o.gamma, o.ct, o.cfl, o.adv_speed = scheme, alpha_mode, gamma, ct, cfl, adv_speed
-        if eps is not None:
-            o.eps_mode, o.eps = 1, float(eps)
+        o = make_opts(scheme=scheme, alpha_mode=alpha_mode, eps=eps, gamma=gamma, ct=ct, cfl=cfl,
+                      adv_speed=adv_speed, C=C, q=q, characteristic=characteristic)
         self.grid, self.opts = g, o
         self._stream_val = torch.cuda.current_stream().cuda_stream
         h = ctypes.c_void_p()
@@ -199,8 +218,9 @@ class Solver:
         _check(lib().teno_rhs(self._h, _ptr(U), _ptr(out), _ptr(masks)), "teno_rhs")
         return out
 
-    def face_fluxes(self, U):
-        """Face fluxes, mask and flag words and the Lax-Friedrichs constants of one evaluation."""
+    def face_fluxes(self, U, chi=False):
+        """Face fluxes, mask and flag words and the Lax-Friedrichs constants of one evaluation; with
+        chi, also chi of eq:norm ([nfaces, 24]: field s, side, k at 6 s + 3 side + k)."""
         self._sync_stream()
         U = self._state(U)
         nv, nx, ny = self.nvar, self.nx, self.ny
@@ -208,12 +228,15 @@ class Solver:
         Fy = torch.empty((nv, ny + 1, nx), dtype=self.dtype, device="cuda") if self.sys == EULER2D else None
         masks = torch.empty(self.nfaces, dtype=torch.int32, device="cuda")
         flags = torch.empty(self.nfaces, dtype=torch.int32, device="cuda")
+        chis = torch.empty((self.nfaces, 24), dtype=self.dtype, device="cuda") if chi else None
         alpha = torch.zeros(8, dtype=torch.float64, device="cuda")
-        _check(lib().teno_face_fluxes(self._h, _ptr(U), _ptr(Fx), _ptr(Fy), _ptr(masks), _ptr(flags), _ptr(alpha)),
-               "teno_face_fluxes")
+        _check(lib().teno_face_fluxes(self._h, _ptr(U), _ptr(Fx), _ptr(Fy), _ptr(masks), _ptr(flags), _ptr(chis),
+                                      _ptr(alpha)), "teno_face_fluxes")
         out = dict(Fx=Fx, masks=masks, flags=flags, alpha=alpha)
         if Fy is not None:
             out["Fy"] = Fy
+        if chis is not None:
+            out["chi"] = chis
         return out
 
     def rhs_frozen(self, U, masks, alpha, out=None):
@@ -230,9 +253,18 @@ class Solver:
         _check(lib().teno_step(self._h, _ptr(self._state(U)), float(dt)), "teno_step")
         return U
 
-    def run(self, U, nsteps, dt=0.0, graph=True):
+    def run(self, U, nsteps, dt=0.0, graph=True, check_every=0):
+        """nsteps SSP-RK3 steps in place. check_every > 0: the device status is read every
+        check_every steps; a failure raises TenoError with .steps_done, the number of steps that
+        completed before the one it was detected in."""
         self._sync_stream()
-        _check(lib().teno_run(self._h, _ptr(self._state(U)), int(nsteps), float(dt), 1 if graph else 0), "teno_run")
+        done = ctypes.c_int32(0)
+        code = lib().teno_run(self._h, _ptr(self._state(U)), int(nsteps), float(dt), 1 if graph else 0,
+                              int(check_every), ctypes.byref(done))
+        if code != 0:
+            err = TenoError(code, "teno_run")
+            err.steps_done = done.value
+            raise err
         return U
 
     def poll(self):
@@ -372,16 +404,14 @@ class Batch:
     """Many independent Euler problems advanced together (one packed state buffer)."""
 
     def __init__(self, problems, dtype=torch.float64, cfl=0.5, gamma=1.4, scheme=TENO7X, alpha_mode=0, eps=None,
-                 ct=1e-5):
+                 ct=1e-5, C=1.0, q=6, characteristic=1):
         n = len(problems)
         grids = (Grid * n)()
         for k, pr in enumerate(problems):
             grids[k] = Grid(pr.sys, pr.nx, pr.ny, pr.bc_x, pr.bc_y, F64 if dtype == torch.float64 else F32,
                             pr.x0, pr.x1, pr.y0, pr.y1)
-        o = default_opts()
-        o.cfl, o.gamma, o.scheme, o.alpha_mode, o.ct = cfl, gamma, scheme, alpha_mode, ct
-        if eps is not None:
-            o.eps_mode, o.eps = 1, float(eps)
+        o = make_opts(scheme=scheme, alpha_mode=alpha_mode, eps=eps, gamma=gamma, ct=ct, cfl=cfl, C=C, q=q,
+                      characteristic=characteristic)
         self.dtype = dtype
         self.problems = problems
         self._stream_val = torch.cuda.current_stream().cuda_stream

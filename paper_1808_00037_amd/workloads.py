@@ -332,3 +332,16 @@ def shock_tube(kind, n=200):
         raise ValueError(kind)
     return Problem(kind, EULER1D, n, 1, 0.0, x1, 0.0, 1.0, OUTFLOW, OUTFLOW, conserved_1d(rho, u, p),
                    cfl=0.6, meta=dict(t_end=t_end))
+
+
+def colliding_streams(n=200, p0=1e-4):
+    """Two cold streams meeting head on (periodic, unit density, velocity +1 on [0.25, 0.75) and -1
+    elsewhere, pressure p0 far below the kinetic energy): a state that the scheme, which has no
+    positivity limiter, drives to a negative pressure after some steps. Used to check that a failing
+    step is detected and reported."""
+    x = cell_centres(0.0, 1.0, n)
+    u = np.where(np.abs(x - 0.5) < 0.25, 1.0, -1.0)
+    rho = np.ones_like(x)
+    p = np.full_like(x, p0)
+    return Problem("colliding_streams", EULER1D, n, 1, 0.0, 1.0, 0.0, 1.0, PERIODIC, PERIODIC,
+                   conserved_1d(rho, u, p), cfl=0.5)

@@ -15,16 +15,23 @@ from oracle import oracle as O
 from paper_1808_00037_amd import teno as T
 
 REL_TOL = 1e-12
+# chi of eq:norm goes through differences of neighbouring values (eq:smooth_expl) that cancel on
+# smooth data, then through the power q: two evaluations that group the arithmetic differently agree
+# to about 1e-11 absolute (measured at most 7.5e-12); the decisions themselves are compared bit for bit
+CHI_TOL = 1e-10
 
 
-def oracle_cfg(pr, scheme=O.TENO7X, eps=None, alpha_mode=0, ct=1e-5):
+def oracle_cfg(pr, scheme=O.TENO7X, eps=None, alpha_mode=0, ct=1e-5, C=1.0, q=6, characteristic=1):
     return O.Config(pr.sys, pr.nx, pr.ny, pr.x0, pr.x1, pr.y0, pr.y1, pr.bc_x, pr.bc_y, scheme=scheme,
-                    alpha_mode=alpha_mode, gamma=pr.gamma, eps=eps, ct=ct)
+                    alpha_mode=alpha_mode, gamma=pr.gamma, eps=eps, ct=ct, C=C, q=q,
+                    characteristic=characteristic)
 
 
-def solver_for(pr, dtype=torch.float64, scheme=T.TENO7X, eps=None, alpha_mode=0, ct=1e-5):
+def solver_for(pr, dtype=torch.float64, scheme=T.TENO7X, eps=None, alpha_mode=0, ct=1e-5, C=1.0, q=6,
+               characteristic=1):
     return T.Solver(pr.sys, pr.nx, pr.ny, pr.x0, pr.x1, pr.y0, pr.y1, pr.bc_x, pr.bc_y, dtype=dtype,
-                    scheme=scheme, eps=eps, alpha_mode=alpha_mode, cfl=pr.cfl, gamma=pr.gamma, ct=ct)
+                    scheme=scheme, eps=eps, alpha_mode=alpha_mode, cfl=pr.cfl, gamma=pr.gamma, ct=ct,
+                    C=C, q=q, characteristic=characteristic)
 
 
 def _phys_flux_mag(sys, U, direction, gamma=1.4, adv=1.0):
@@ -65,20 +72,26 @@ def face_scale(pr, U, direction):
     return out
 
 
-def compare_faces(pr, U_np, scheme=O.TENO7X, eps=None, alpha_mode=0, solver=None, ct=1e-5):
-    """Run both sides on one state; return a report dict (asserting nothing)."""
-    cfg = oracle_cfg(pr, scheme, eps, alpha_mode, ct)
+def compare_faces(pr, U_np, scheme=O.TENO7X, eps=None, alpha_mode=0, solver=None, ct=1e-5, C=1.0, q=6,
+                  characteristic=1):
+    """Run both sides on one state; return a report dict (asserting nothing). The GPU's chi of
+    eq:norm is compared with the oracle's (chi_worst) and its own flags are checked against it
+    (chi_flag_mismatch: a flag that disagrees with the GPU's chi away from rounding of C_T)."""
+    opts = dict(scheme=scheme, eps=eps, alpha_mode=alpha_mode, ct=ct, C=C, q=q, characteristic=characteristic)
+    cfg = oracle_cfg(pr, **opts)
     _, ex = O.rhs(cfg, U_np, want_faces=True)
-    sv = solver or solver_for(pr, scheme=scheme, eps=eps, alpha_mode=alpha_mode, ct=ct)
+    sv = solver or solver_for(pr, **opts)
     U = torch.from_numpy(np.ascontiguousarray(U_np)).cuda()
-    g = sv.face_fluxes(U)
+    g = sv.face_fluxes(U, chi=True)
     torch.cuda.synchronize()
     sv.poll()
     nfx = pr.ny * (pr.nx + 1)
     masks_g = g["masks"].cpu().numpy().view(np.uint32)
     flags_g = g["flags"].cpu().numpy().view(np.uint32)
+    chi_g = g["chi"].double().cpu().numpy()
     rep = dict(alpha_gpu=g["alpha"].cpu().numpy(), alpha_orc=ex["alpha"], nfaces=0, worst=0.0, flips=0,
-               flips_near_ct=0, flag_diffs=0)
+               flips_near_ct=0, flag_diffs=0, chi_worst=0.0, chi_flag_mismatch=0)
+    nbits = 6 * np.asarray(U_np).shape[0]
     dirs = [("x", 0, g["Fx"], ex["Fx"], ex["masks_x"], ex["flags_x"], ex["chi_x"], slice(0, nfx))]
     if pr.sys == O.EULER2D:
         dirs.append(("y", 1, g["Fy"], ex["Fy"], ex["masks_y"], ex["flags_y"], ex["chi_y"], slice(nfx, None)))
@@ -86,6 +99,12 @@ def compare_faces(pr, U_np, scheme=O.TENO7X, eps=None, alpha_mode=0, solver=None
         Fg = Fg.cpu().numpy()
         mg = masks_g[sec].reshape(mo.shape)
         fg = flags_g[sec].reshape(fo.shape)
+        cg = chi_g[sec].reshape(chi.shape)
+        rep["chi_worst"] = max(rep["chi_worst"], float(np.abs(cg[..., :nbits] - chi[..., :nbits]).max()))
+        # the GPU's flags follow its own chi (a decision within rounding of C_T may go either way)
+        bits = ((fg[..., None] >> np.arange(nbits, dtype=np.uint32)) & 1).astype(bool)
+        own = cg[..., :nbits] >= ct
+        rep["chi_flag_mismatch"] += int(np.count_nonzero((bits != own) & (np.abs(cg[..., :nbits] / ct - 1) >= NEAR_CT)))
         same = mg == mo
         # flags: every difference must sit within rounding of the cut-off
         fdiff = fg != fo
@@ -110,8 +129,170 @@ def compare_faces(pr, U_np, scheme=O.TENO7X, eps=None, alpha_mode=0, solver=None
     return rep
 
 
+def census_line(rep):
+    """One line of the selection census of a face comparison."""
+    return (f"faces {rep['nfaces']}, flag words differing {rep['flag_diffs']} (within rounding of C_T: "
+            f"{rep['flips_near_ct']}), mask words differing {rep['flips']} (unexplained: "
+            f"{rep.get('mask_diffs_unexplained', 0)}), worst face error {rep['worst']:.2e}")
+
+
 def assert_face_parity(rep):
+    print("[census]", census_line(rep), f"chi difference {rep['chi_worst']:.1e}", flush=True)
     assert rep["flag_diffs"] == rep["flips_near_ct"], rep
+    assert rep["chi_worst"] <= CHI_TOL and rep["chi_flag_mismatch"] == 0, rep
     assert rep.get("mask_diffs_unexplained", 0) == 0, rep
     assert rep["worst"] <= REL_TOL, rep
     assert np.allclose(rep["alpha_gpu"], rep["alpha_orc"], rtol=1e-14, atol=0), rep
+
+
+NEAR_CT = 1e-9      # a cut-off decision within this relative distance of C_T may go either way
+
+
+def near_bits(chi, ct):
+    """Per face, a 24-bit word with bit 6s+3side+k set where chi of that decision lies within
+    rounding (NEAR_CT, relative) of C_T. chi: [..., 24]."""
+    near = np.abs(chi / ct - 1.0) < NEAR_CT
+    w = np.zeros(chi.shape[:-1], dtype=np.uint32)
+    for b in range(chi.shape[-1]):
+        w |= near[..., b].astype(np.uint32) << np.uint32(b)
+    return w
+
+
+class FaceCensus:
+    """The oracle's selection of every face of a 2D state, gathered strip by strip (masks, flags,
+    which decisions sit within rounding of C_T, optionally the face fluxes), then compared with the
+    GPU's words:
+      * a flag bit may differ only where the oracle's chi of that decision is near C_T;
+      * a mask word may differ only where a flag of the face or of a neighbour face along the line
+        (the faces eq:vec reads) is near C_T."""
+
+    def __init__(self, pr, ct=1e-5, keep_flux=False):
+        ny, nx = pr.ny, pr.nx
+        self.pr, self.ct = pr, ct
+        self.mx = np.zeros((ny, nx + 1), np.uint32)
+        self.my = np.zeros((ny + 1, nx), np.uint32)
+        self.fx = np.zeros_like(self.mx)
+        self.fy = np.zeros_like(self.my)
+        self.nx_ = np.zeros_like(self.mx)
+        self.ny_ = np.zeros_like(self.my)
+        nv = pr.U0.shape[0]
+        self.Fx = np.zeros((nv, ny, nx + 1)) if keep_flux else None
+        self.Fy = np.zeros((nv, ny + 1, nx)) if keep_flux else None
+
+    def on_faces(self, j0, j1, f):
+        fy = f["masks_y"].shape[0]
+        self.mx[j0:j1] = f["masks_x"]
+        self.fx[j0:j1] = f["flags_x"]
+        self.nx_[j0:j1] = near_bits(f["chi_x"], self.ct)
+        self.my[j0:j0 + fy] = f["masks_y"]
+        self.fy[j0:j0 + fy] = f["flags_y"]
+        self.ny_[j0:j0 + fy] = near_bits(f["chi_y"], self.ct)
+        if self.Fx is not None:
+            self.Fx[:, j0:j1] = f["Fx"]
+            self.Fy[:, j0:j0 + fy] = f["Fy"]
+
+    def compare(self, masks_g, flags_g=None):
+        """masks_g/flags_g: the GPU's words of every face (x-faces then y-faces, uint32)."""
+        nfx = self.mx.size
+        rep = dict(faces=nfx + self.my.size, flag_diffs=0, flag_diffs_unexplained=0, mask_diffs=0,
+                   mask_diffs_unexplained=0)
+        diffs = {}
+        for d, (mo, fo, nb) in enumerate(((self.mx, self.fx, self.nx_), (self.my, self.fy, self.ny_))):
+            sec = slice(0, nfx) if d == 0 else slice(nfx, None)
+            mg = masks_g[sec].reshape(mo.shape)
+            if flags_g is not None:
+                fg = flags_g[sec].reshape(fo.shape)
+                x = fg ^ fo
+                rep["flag_diffs"] += int(np.count_nonzero(x))
+                rep["flag_diffs_unexplained"] += int(np.count_nonzero(x & ~nb))
+            md = mg != mo
+            ax = 1 if d == 0 else 0
+            near = nb != 0
+            near_line = near.copy()
+            if ax == 1:
+                near_line[:, 1:] |= near[:, :-1]
+                near_line[:, :-1] |= near[:, 1:]
+            else:
+                near_line[1:] |= near[:-1]
+                near_line[:-1] |= near[1:]
+            rep["mask_diffs"] += int(np.count_nonzero(md))
+            rep["mask_diffs_unexplained"] += int(np.count_nonzero(md & ~near_line))
+            diffs[d] = md
+        rep["near_ct_faces"] = int(np.count_nonzero(self.nx_) + np.count_nonzero(self.ny_))
+        return rep, diffs
+
+
+def census_text(rep):
+    return (f"faces {rep['faces']}, decisions near C_T {rep['near_ct_faces']}, flag words differing "
+            f"{rep['flag_diffs']} (unexplained {rep['flag_diffs_unexplained']}), mask words differing "
+            f"{rep['mask_diffs']} (unexplained {rep['mask_diffs_unexplained']})")
+
+
+def cells_touched(diffs, shape, radius, periodic):
+    """Cells whose value a differing selection at these faces can reach within `radius` more cells
+    along rows and columns (x-face f of a row touches cells f-1 and f; y-face likewise)."""
+    from scipy import ndimage
+    ny, nx = shape
+    hit = np.zeros(shape, bool)
+    mx, my = diffs[0], diffs[1]
+    hit[:, :] |= mx[:, :nx] | mx[:, 1:]           # cells right and left of each x-face
+    hit[:, :] |= my[:ny, :] | my[1:, :]
+    if radius > 0 and hit.any():
+        hit = ndimage.maximum_filter(hit.astype(np.uint8), size=2 * radius + 1,
+                                     mode="wrap" if periodic else "nearest").astype(bool)
+    return hit
+
+
+def _near_line(nb, ax):
+    near = nb != 0
+    out = near.copy()
+    if ax == 1:
+        out[:, 1:] |= near[:, :-1]
+        out[:, :-1] |= near[:, 1:]
+    else:
+        out[1:] |= near[:-1]
+        out[:-1] |= near[1:]
+    return out
+
+
+def trajectory_census(pr, cfg, U0, nsteps, gpu_masks=None, dt=0.0):
+    """The oracle's SSP-RK3 trajectory taken stage by stage (oracle.step_stages, bitwise its run())
+    with every face's selection in view. gpu_masks ([nsteps, 3, nfaces] words recorded by the GPU)
+    are compared face by face: a differing word is explained when a cut-off decision of the face or
+    of a neighbour face along its line lies within rounding of C_T, or when an earlier stage already
+    differed (its state then differs too). Returns (final state, alpha [nsteps, 3, 8], dt [nsteps],
+    census dict)."""
+    U = np.ascontiguousarray(U0, dtype=np.float64).copy()
+    alphas, dts = [], []
+    rep = dict(words=0, mask_diffs=0, unexplained=0, downstream=0, near_ct_faces=0)
+    diverged = False
+    two_d = pr.sys == O.EULER2D
+    for n in range(nsteps):
+        faces = []
+        U, info = O.step_stages(cfg, U, dt=dt, cfl=pr.cfl, on_faces=lambda s, j0, j1, f: faces.append(f))
+        alphas.append(info["alpha"])
+        dts.append(info["dt"])
+        if gpu_masks is None:
+            continue
+        for s, f in enumerate(faces):
+            parts = [("x", f["masks_x"], near_bits(f["chi_x"], cfg.ct), 1)]
+            if two_d:
+                parts.append(("y", f["masks_y"], near_bits(f["chi_y"], cfg.ct), 0))
+            off = 0
+            for _, mo, nb, ax in parts:
+                mg = np.asarray(gpu_masks[n, s, off:off + mo.size]).view(np.uint32).reshape(mo.shape)
+                off += mo.size
+                md = mg != mo
+                nd = int(np.count_nonzero(md))
+                rep["words"] += mo.size
+                rep["mask_diffs"] += nd
+                rep["near_ct_faces"] += int(np.count_nonzero(nb))
+                if nd:
+                    bad = int(np.count_nonzero(md & ~_near_line(nb, ax)))
+                    if diverged:
+                        rep["downstream"] += bad
+                    else:
+                        rep["unexplained"] += bad
+            if rep["mask_diffs"]:
+                diverged = True
+    return U, np.array(alphas), np.array(dts), rep

@@ -49,6 +49,7 @@ def test_default_opts_are_the_papers_parameters(T):
     T.lib().teno_default_opts(ctypes.byref(o))
     assert o.scheme == T.TENO7X and o.alpha_mode == 0 and o.eps_mode == 0
     assert o.gamma == 1.4 and o.ct == 1e-5 and o.cfl == 0.5 and o.adv_speed == 1.0
+    assert o.C == 1.0 and o.q == 6 and o.characteristic == 1
 
 
 def test_status_strings(T):
@@ -78,7 +79,8 @@ def test_create_rejects_invalid_grids_before_touching_the_device(T, bad):
 
 
 @pytest.mark.parametrize("field,value", [("gamma", 1.0), ("ct", 0.0), ("ct", 0.5), ("cfl", 0.0), ("scheme", 2),
-                                         ("alpha_mode", 3), ("eps_mode", 2)])
+                                         ("alpha_mode", 3), ("eps_mode", 2), ("q", 0), ("q", 13), ("C", 0.0),
+                                         ("C", float("inf")), ("characteristic", 2)])
 def test_create_rejects_invalid_options(T, field, value):
     o = T.Opts()
     T.lib().teno_default_opts(ctypes.byref(o))
@@ -93,7 +95,7 @@ def test_null_arguments(T):
     assert L.teno_create(None, None, None, None) == -1
     assert L.teno_destroy(None) == -1
     assert L.teno_rhs(None, None, None, None) == -1
-    assert L.teno_run(None, None, 1, 0.0, 0) == -1
+    assert L.teno_run(None, None, 1, 0.0, 0, 0, None) == -1
     assert L.teno_batch_destroy(None) == -1
     assert L.teno_batch_set_shape(None, 4, 4, 1) == -1
 
@@ -127,3 +129,31 @@ def test_binding_rejects_host_buffers():
     for bad in (torch.zeros(10, dtype=torch.int32), None, "masks"):
         with pytest.raises(ValueError):
             _buf(bad, _WORD_TYPES, 10, "masks")
+
+
+def test_workspace_bytes(T):
+    """The device memory a context allocates by itself, as a function of the problem and of the
+    reverse sweep's checkpoint interval (host arithmetic only)."""
+    o = T.Opts()
+    T.lib().teno_default_opts(ctypes.byref(o))
+    L = T.lib()
+
+    def ws(g, ck=0):
+        return L.teno_workspace_bytes(ctypes.byref(g), ctypes.byref(o), ck)
+
+    g2 = _grid(T, nx=4096, ny=4096)
+    state = 4 * 4096 * 4096 * 8
+    ctrl = ws(g2) - 3 * state                       # control block: the rest
+    assert 0 < ctrl < 1 << 20
+    assert ws(g2, 20) - ws(g2) == (3 * 20 + 3) * state
+    g1 = _grid(T, sys=T.EULER1D, nx=4096, ny=1)
+    assert ws(g1) == ctrl + 2 * 3 * 4096 * 8        # no y-part for one-dimensional systems
+    g32 = _grid(T, dtype=T.F32)
+    assert ws(g32) == ctrl + 3 * 4 * 64 * 32 * 4
+    assert ws(_grid(T, nx=0)) == 0
+    assert ws(g2, -1) == 0
+    bad = T.Opts()
+    T.lib().teno_default_opts(ctypes.byref(bad))
+    bad.q = 0
+    assert L.teno_workspace_bytes(ctypes.byref(g2), ctypes.byref(bad), 0) == 0
+    assert T.workspace_bytes(T.EULER2D, 4096, 4096, ckpt_every=20) == ws(g2, 20)

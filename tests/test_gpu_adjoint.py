@@ -15,7 +15,7 @@ from oracle import oracle as O
 from paper_1808_00037_amd import teno as T
 from paper_1808_00037_amd import workloads as W
 
-from gpu_common import oracle_cfg, solver_for
+from gpu_common import oracle_cfg, solver_for, trajectory_census
 
 pytestmark = pytest.mark.gpu
 
@@ -152,11 +152,12 @@ def test_record_replay_bitwise_and_masks_match_oracle():
     sv.run_replay(U2, rec)
     sv.poll()
     assert torch.equal(U, U2)
-    # the recorded selection equals the oracle's own on the same trajectory (no flips expected here)
-    _, orec = O.run(oracle_cfg(pr), pr.U0, 5, cfl=pr.cfl, record=True)
-    gm = rec["masks"].cpu().numpy().view(np.uint32)
-    assert np.mean(gm == orec["masks"]) > 0.9999
-    assert np.allclose(rec["alpha_dt"].cpu().numpy()[:, 24], orec["dt"], rtol=1e-13)
+    # the recorded selection equals the oracle's own on the same trajectory, word by word; a word may
+    # differ only where a cut-off decision it depends on lies within rounding of C_T
+    _, _, dts, rep = trajectory_census(pr, oracle_cfg(pr), pr.U0, 5, rec["masks"].cpu().numpy())
+    print("[census]", rep, flush=True)
+    assert rep["unexplained"] == 0 and rep["downstream"] == 0, rep
+    assert np.allclose(rec["alpha_dt"].cpu().numpy()[:, 24], dts, rtol=1e-13)
 
 
 def test_trajectory_gradient_matches_central_differences():

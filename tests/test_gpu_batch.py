@@ -110,8 +110,9 @@ def test_single_precision_batch():
     assert err < 1e-4, err
 
 
-@pytest.mark.parametrize("opts", [dict(scheme=T.TENO5), dict(alpha_mode=1), dict(eps=1e-6), dict(ct=1e-4)],
-                         ids=["teno5", "scalar_alpha", "constant_eps", "ct_1e-4"])
+@pytest.mark.parametrize("opts", [dict(scheme=T.TENO5), dict(alpha_mode=1), dict(eps=1e-6), dict(ct=1e-4),
+                                  dict(C=2.0, q=4), dict(characteristic=0)],
+                         ids=["teno5", "scalar_alpha", "constant_eps", "ct_1e-4", "C2_q4", "componentwise"])
 def test_batch_options_match_single_runs(opts):
     # every scheme option reaches the batched kernels as it reaches the single-problem solver
     probs = _problems()

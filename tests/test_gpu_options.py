@@ -1,0 +1,144 @@
+"""The scheme options of the C ABI against the oracle on the GPU (gfx950): the constants C and q of
+eq:TENO1, the reconstruction per conserved component instead of in characteristic variables
+(Remark 3), the chi output of eq:norm (compared in every face comparison), the failing-step report
+of checked runs, and the device memory a context allocates against teno_workspace_bytes."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_1808_00037_amd import teno as T
+from paper_1808_00037_amd import workloads as W
+
+from gpu_common import assert_face_parity, compare_faces, oracle_cfg, solver_for
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(*a):
+    print("[case]", *a, flush=True)
+
+
+@pytest.mark.parametrize("C,q", [(0.5, 2), (2.0, 4), (1.0, 8), (3.0, 1), (1.0, 12)])
+def test_constants_C_and_q(C, q):
+    _case("C, q", C, q)
+    pr = W.euler2d(50 + q, n=130, ny=70)
+    assert_face_parity(compare_faces(pr, pr.U0, C=C, q=q))
+    pa = W.advection(6, 200)
+    U = pa.U0.copy()
+    U[0, 0, 70:130] += 0.6
+    assert_face_parity(compare_faces(pa, U, C=C, q=q))
+
+
+@pytest.mark.parametrize("bc", [O.PERIODIC, O.OUTFLOW], ids=["periodic", "outflow"])
+def test_componentwise_faces(bc):
+    _case("component-wise", bc)
+    pr = W.euler2d(61, n=250, ny=66)
+    pr.bc_x = pr.bc_y = bc
+    assert_face_parity(compare_faces(pr, pr.U0, characteristic=0))
+    p1 = W.euler1d(62, n=400)
+    p1.bc_x = bc
+    assert_face_parity(compare_faces(p1, p1.U0, characteristic=0))
+    assert_face_parity(compare_faces(p1, p1.U0, characteristic=0, scheme=O.TENO5, eps=p1.dx ** 3))
+
+
+@pytest.mark.parametrize("opts", [dict(characteristic=0), dict(C=2.0, q=4), dict(characteristic=0, q=3)],
+                         ids=["componentwise", "C2q4", "componentwise_q3"])
+def test_options_step_parity(opts):
+    pr = W.euler2d(63, n=250, ny=64)
+    _case("steps with", opts)
+    cfg = oracle_cfg(pr, **opts)
+    Uo = O.run(cfg, pr.U0, 6, cfl=pr.cfl)
+    sv = solver_for(pr, **opts)
+    U = torch.from_numpy(pr.U0.copy()).cuda()
+    sv.run(U, 6, graph=True)
+    sv.poll()
+    err = np.abs(U.cpu().numpy() - Uo).max() / np.abs(Uo).max()
+    _case("max relative difference", err)
+    assert err < 1e-11, err
+
+
+def test_componentwise_adjoint_is_refused():
+    pr = W.euler2d(64, n=32, ny=24)
+    sv = solver_for(pr, characteristic=0)
+    U = torch.from_numpy(pr.U0.copy()).cuda()
+    masks = sv.masks_buffer()
+    sv.rhs(U, masks=masks)
+    with pytest.raises(T.TenoError) as e:
+        sv.rhs_vjp(U, masks, sv.last_alpha(), torch.ones_like(U))
+    assert e.value.code == -2
+    sv.poll()
+
+
+def _oracle_failing_step(pr, nmax):
+    """Index of the first step of the oracle's trajectory that produces a non-physical state (in any
+    of its stages), and the oracle's state before it."""
+    cfg = oracle_cfg(pr)
+    U = pr.U0.copy()
+
+    def physical(V):
+        rho, m, E = V[0, 0], V[1, 0], V[2, 0]
+        return rho.min() > 0 and (0.4 * (E - 0.5 * m * m / rho)).min() > 0
+
+    for n in range(nmax):
+        try:
+            U1, _ = O.step_stages(cfg, U, cfl=pr.cfl)
+        except O.OracleError:
+            return n, U
+        if not physical(U1):
+            return n, U
+        U = U1
+    return None, U
+
+
+@pytest.mark.parametrize("check_every,graph", [(1, True), (4, True), (7, False), (100, True)])
+def test_checked_run_reports_the_failing_step(check_every, graph):
+    """Colliding cold streams reach a negative pressure; the checked run stops and reports the index
+    of the step in which the device saw it, the step in which the oracle's trajectory first leaves
+    the physical states, whatever the check interval. The library raises the error word and every
+    kernel exits normally."""
+    pr = W.colliding_streams()
+    n_fail, U_before = _oracle_failing_step(pr, 60)
+    assert n_fail is not None and n_fail > 3
+    _case("oracle: first non-physical step", n_fail, "check every", check_every, "graph", graph)
+    sv = solver_for(pr)
+    U = torch.from_numpy(pr.U0.copy()).cuda()
+    with pytest.raises(T.TenoError) as e:
+        sv.run(U, 60, graph=graph, check_every=check_every)
+    _case("device: status", e.value.code, "steps done", e.value.steps_done)
+    assert e.value.code in (-5, -4)
+    assert e.value.steps_done == n_fail
+    sv.poll()                               # cleared by the run
+    # the same context runs on afterwards: the steps before the failure reproduce the oracle's
+    U = torch.from_numpy(pr.U0.copy()).cuda()
+    sv.run(U, n_fail, graph=graph, check_every=check_every)
+    err = np.abs(U.cpu().numpy() - U_before).max() / np.abs(U_before).max()
+    assert err < 1e-10, err
+
+
+def test_unchecked_run_leaves_the_failure_to_poll():
+    pr = W.colliding_streams()
+    sv = solver_for(pr)
+    U = torch.from_numpy(pr.U0.copy()).cuda()
+    sv.run(U, 30, graph=True)               # no synchronisation, no error here
+    with pytest.raises(T.TenoError):
+        sv.poll()
+    sv.poll()
+
+
+def test_workspace_bytes_match_the_allocation():
+    pr = W.euler2d(65, n=2048)
+    ws = T.workspace_bytes(T.EULER2D, 2048, 2048)
+    U = torch.from_numpy(pr.U0).cuda()
+    sv0 = solver_for(W.euler2d(66, n=16))   # the library's code and runtime set up beforehand
+    sv0.step(torch.from_numpy(W.euler2d(66, n=16).U0).cuda())
+    sv0.poll()
+    torch.cuda.synchronize()
+    free0, _ = torch.cuda.mem_get_info()
+    sv = solver_for(pr)
+    sv.step(U)                              # the stage scratch is allocated at the first step
+    sv.poll()
+    free1, _ = torch.cuda.mem_get_info()
+    used = free0 - free1
+    _case("workspace bytes", ws, "device memory taken by the context", used)
+    assert abs(used - ws) <= 0.02 * ws + (64 << 20), (used, ws)

@@ -13,7 +13,7 @@ from oracle import oracle as O
 from paper_1808_00037_amd import teno as T
 from paper_1808_00037_amd import workloads as W
 
-from gpu_common import assert_face_parity, compare_faces, oracle_cfg, solver_for
+from gpu_common import assert_face_parity, compare_faces, oracle_cfg, solver_for, trajectory_census
 
 pytestmark = pytest.mark.gpu
 
@@ -61,6 +61,8 @@ def test_euler2d_faces_outflow():
 def test_euler2d_scalar_alpha():
     pr = W.euler2d(6, n=70, ny=66)
     assert_face_parity(compare_faces(pr, pr.U0, alpha_mode=1))
+    p1 = W.euler1d(6, n=300)
+    assert_face_parity(compare_faces(p1, p1.U0, alpha_mode=1))
 
 
 def _burgers_shocked(n):
@@ -106,7 +108,7 @@ def test_cutoff_parameter(ct):
     assert_face_parity(compare_faces(pa, U, ct=ct))
 
 
-@pytest.mark.parametrize("sys", [O.ADV1D, O.EULER1D])
+@pytest.mark.parametrize("sys", [O.ADV1D, O.EULER1D, O.EULER2D])
 def test_teno5_faces(sys):
     """TENO5 base scheme (Table 1). Advection keeps the paper's eps = 1e-40. For Euler, eps = 1e-40
     leaves the cut-off of characteristic fields that are constant up to rounding (the acoustic
@@ -117,9 +119,49 @@ def test_teno5_faces(sys):
         U = pr.U0.copy()
         U[0, 0, 150:] -= 0.7
         assert_face_parity(compare_faces(pr, U, scheme=O.TENO5))
-    else:
+    elif sys == O.EULER1D:
         pr = W.euler1d(3, n=333)
         assert_face_parity(compare_faces(pr, pr.U0, scheme=O.TENO5, eps=pr.dx ** 3))
+    else:
+        for nx, ny, bc in ((250, 190, O.PERIODIC), (97, 130, O.OUTFLOW)):
+            pr = W.euler2d(nx + 7 * ny, n=nx, ny=ny)
+            pr.bc_x = pr.bc_y = bc
+            _print_case("teno5 euler2d", nx, ny, bc)
+            assert_face_parity(compare_faces(pr, pr.U0, scheme=O.TENO5, eps=pr.dx ** 3))
+
+
+@pytest.mark.parametrize("scheme", [T.TENO7X, T.TENO5], ids=["teno7x", "teno5"])
+@pytest.mark.parametrize("nx,ny,bc", [(250, 190, O.PERIODIC), (245, 64, O.OUTFLOW), (488, 40, O.PERIODIC)])
+def test_euler2d_steps_with_whole_line_tiles(nx, ny, bc, scheme):
+    """Stepped parity of the benchmark's kernels: lines of at least 4 segments of 61 cells, so that the
+    x-stage kernel stages whole-line tiles and applies its fused stage epilogue (U^n and the y-part
+    copied into LDS), replayed from the captured graph; steps 2 and later use the constants and dt
+    that the stage epilogue's maxima produce. Ten steps against the oracle."""
+    pr = W.euler2d(nx * 3 + ny, n=nx, ny=ny)
+    pr.bc_x = pr.bc_y = bc
+    eps = pr.dx ** 3 if scheme == T.TENO5 else None
+    _print_case("whole-line tiles", nx, ny, bc, scheme)
+    nsteps = 10
+    cfg = oracle_cfg(pr, scheme=scheme, eps=eps)
+    sv = solver_for(pr, scheme=scheme, eps=eps)
+    U = torch.from_numpy(pr.U0.copy()).cuda()
+    sv.run(U, nsteps, graph=True)
+    sv.poll()
+    # the recording kernels take the same steps; their selection is compared with the oracle's
+    U2 = torch.from_numpy(pr.U0.copy()).cuda()
+    grec = sv.run_record(U2, nsteps, 5)
+    sv.poll()
+    assert torch.equal(U2, U)
+    gm = grec["masks"].cpu().numpy()
+    Uo, alpha, dts, rep = trajectory_census(pr, cfg, pr.U0, nsteps, gm)
+    print("[census]", rep, flush=True)
+    assert rep["unexplained"] == 0, rep
+    err = np.abs(U.cpu().numpy() - Uo).max() / np.abs(Uo).max()
+    _print_case("max relative difference", err, "last dt", sv.last_dt(), dts[-1])
+    if rep["mask_diffs"] == 0:
+        assert err < 1e-11, err
+    assert abs(sv.last_dt() - dts[-1]) <= 1e-13 * dts[-1]
+    assert np.allclose(grec["alpha_dt"].cpu().numpy()[:, :24].reshape(nsteps, 3, 8), alpha, rtol=1e-13, atol=0)
 
 
 @pytest.mark.parametrize("n", [1, 2, 3, 7])
