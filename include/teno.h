@@ -41,7 +41,8 @@ typedef enum {
     TENO_E_HIP = -3,          /* a HIP runtime call failed */
     TENO_E_NONFINITE = -4,    /* a NaN/Inf reached a smoothness measure or state */
     TENO_E_NONPHYSICAL = -5,  /* density, pressure or Roe sound speed squared <= 0 */
-    TENO_E_STATE = -6         /* call not valid in the context's current state */
+    TENO_E_STATE = -6,        /* call not valid in the context's current state */
+    TENO_E_CAPACITY = -7      /* the problem needs more than the fixed scratch of teno_step_noalloc */
 } teno_status;
 
 typedef enum { TENO_ADV1D = 0, TENO_EULER1D = 1, TENO_EULER2D = 2, TENO_BURGERS1D = 3 } teno_system;
@@ -143,6 +144,23 @@ teno_status teno_rhs_frozen(teno_ctx *ctx, const void *U, const uint32_t *masks,
  * dt_fixed > 0 sets dt; otherwise dt = cfl / max_j((|u|+c)/dx [+ (|v|+c)/dy]) from U on the
  * device (no host synchronisation). U is updated in place. */
 teno_status teno_step(teno_ctx *ctx, void *U, double dt_fixed);
+
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation): one SSP-RK3 step exactly as teno_step takes it, without a
+ * context and without allocating anything. The control block and the stage scratch live in one fixed
+ * device array of TENO_NOALLOC_SCRATCH_BYTES per GPU, part of the library's code object, held until
+ * the process ends. A problem needing more (control block, two stage states, plus the y-part of dU/dt
+ * for 2D Euler: about 96 bytes per cell for 2D Euler in double precision, i.e. up to about 174k cells)
+ * is refused with TENO_E_CAPACITY before anything is enqueued; TENO_E_ARG for an invalid grid, opts
+ * or pointer. U (device, [nvar][ny][nx], caller-owned) is advanced in place on `stream`
+ * (hipStream_t). dt_fixed > 0 sets dt, else the CFL rule. status_dev (nullable, device int32)
+ * receives TENO_OK or the device failure of this step (as teno_poll would report it); dt_dev
+ * (nullable, device double) the step's dt. Every call on a GPU shares that GPU's scratch and starts
+ * by clearing it, so calls that overlap on one GPU (several streams or threads) race and must be
+ * ordered by the caller. Enqueues only; TENO_E_HIP if the scratch cannot be located. */
+#define TENO_NOALLOC_SCRATCH_BYTES (16u << 20)
+teno_status teno_step_noalloc(const teno_grid *grid, const teno_opts *opts, void *U, double dt_fixed,
+                              void *stream, int32_t *status_dev, double *dt_dev);
 
 /* nsteps calls of teno_step. use_graph = 1 captures one step into a HIP graph on first use and
  * replays it (identical results; fewer launches).

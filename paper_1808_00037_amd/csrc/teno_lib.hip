@@ -87,6 +87,55 @@ void teno_fill_derived(teno_ctx *c)
 }
 
 // ------------------------------------------------------------------------------------------------
+// Fixed scratch of teno_step_noalloc: the control block, then the stage states. Each device holds its
+// own copy; host code reaches it only through the device address hipGetSymbolAddress returns for
+// that device (the array's name is a host-side stand-in).
+// ------------------------------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[TENO_NOALLOC_SCRATCH_BYTES];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static std::mutex noalloc_mutex;
+static void *noalloc_ptr[NOALLOC_MAX_DEVICES];
+
+// Device address of this device's scratch (looked up once per device, with that device current).
+static teno_status noalloc_scratch(void **out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= NOALLOC_MAX_DEVICES) return TENO_E_HIP;
+    std::lock_guard<std::mutex> lock(noalloc_mutex);
+    if (!noalloc_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return TENO_E_HIP;
+        }
+        noalloc_ptr[dev] = p;
+    }
+    *out = noalloc_ptr[dev];
+    return TENO_OK;
+}
+
+// Zero a control block with a kernel (stream-ordered, and a plain kernel node under graph capture).
+static __global__ void zero_ctrl_kernel(Ctrl *ctrl)
+{
+    unsigned *w = (unsigned *)ctrl;
+    for (size_t q = threadIdx.x; q < sizeof(Ctrl) / sizeof(unsigned); q += blockDim.x) w[q] = 0u;
+}
+
+// The step's outcome for the caller: status as teno_poll reports it, and dt.
+static __global__ void noalloc_report_kernel(const Ctrl *ctrl, int32_t *status_dev, double *dt_dev)
+{
+    if (threadIdx.x == 0) {
+        const unsigned e = ctrl->err;
+        if (status_dev)
+            *status_dev = (e & ERR_NONFINITE) ? TENO_E_NONFINITE
+                        : (e & ERR_NONPHYSICAL) ? TENO_E_NONPHYSICAL
+                        : (e & ERR_SELECTION) ? TENO_E_NONFINITE : TENO_OK;
+        if (dt_dev) *dt_dev = ctrl->dt;
+    }
+}
+
+// ------------------------------------------------------------------------------------------------
 // launch helpers
 // ------------------------------------------------------------------------------------------------
 
@@ -383,6 +432,7 @@ const char *teno_status_str(teno_status s)
     case TENO_E_NONFINITE: return "non-finite value";
     case TENO_E_NONPHYSICAL: return "non-physical state";
     case TENO_E_STATE: return "invalid context state";
+    case TENO_E_CAPACITY: return "problem exceeds the fixed scratch of the no-allocation entry point";
     }
     return "unknown status";
 }
@@ -568,6 +618,38 @@ static teno_status read_failure(teno_ctx *c, unsigned *err_at)
         HIP_TRY(hipMemcpy(&c->ctrl_d->err_at, &z[1], sizeof(unsigned), hipMemcpyHostToDevice));
     }
     return err_to_status(w[0]);
+}
+
+teno_status teno_step_noalloc(const teno_grid *grid, const teno_opts *opts, void *U, double dt_fixed, void *stream,
+                              int32_t *status_dev, double *dt_dev)
+{
+    if (!U || !teno_validate(grid, opts)) return TENO_E_ARG;
+    teno_ctx c;                                  // host-side description only: no allocation
+    c.grid = *grid;
+    c.opts = *opts;
+    c.stream = (hipStream_t)stream;
+    teno_fill_derived(&c);
+    const size_t ctrl_bytes = (sizeof(Ctrl) + 255) / 256 * 256;
+    const size_t state = (c.nelem * c.esize + 255) / 256 * 256;
+    const int nstates = grid->sys == TENO_EULER2D ? 3 : 2;
+    if (ctrl_bytes + nstates * state > (size_t)TENO_NOALLOC_SCRATCH_BYTES) return TENO_E_CAPACITY;
+    void *base = nullptr;
+    teno_status st = noalloc_scratch(&base);
+    if (st) return st;
+    char *p = (char *)base;
+    c.ctrl_d = (Ctrl *)p;
+    c.S1 = p + ctrl_bytes;
+    c.S2 = p + ctrl_bytes + state;
+    c.dUy = grid->sys == TENO_EULER2D ? p + ctrl_bytes + 2 * state : nullptr;
+    // the previous call's contents: every ring slot, the constants, dt and the error word start at zero
+    hipLaunchKernelGGL(zero_ctrl_kernel, dim3(1), dim3(256), 0, c.stream, c.ctrl_d);
+    teno_launch_wavespeed(&c, U, 0);
+    teno_enqueue_step(&c, U, dt_fixed, nullptr, nullptr, nullptr, nullptr, nullptr);
+    if (status_dev || dt_dev)
+        hipLaunchKernelGGL(noalloc_report_kernel, dim3(1), dim3(64), 0, c.stream, c.ctrl_d, status_dev, dt_dev);
+    c.S1 = c.S2 = c.dUy = nullptr;               // not the context's to free
+    c.ctrl_d = nullptr;
+    return hipGetLastError() == hipSuccess ? TENO_OK : TENO_E_HIP;
 }
 
 teno_status teno_run(teno_ctx *c, void *U, int32_t nsteps, double dt_fixed, int32_t use_graph, int32_t check_every,

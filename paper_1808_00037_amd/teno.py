@@ -22,7 +22,9 @@ F64, F32 = 0, 1
 NVAR = {ADV1D: 1, EULER1D: 3, EULER2D: 4, BURGERS1D: 1}
 
 STATUS = {0: "ok", -1: "invalid argument", -2: "unsupported", -3: "HIP runtime error",
-          -4: "non-finite value", -5: "non-physical state", -6: "invalid context state"}
+          -4: "non-finite value", -5: "non-physical state", -6: "invalid context state",
+          -7: "problem exceeds the fixed scratch of the no-allocation entry point"}
+NOALLOC_SCRATCH_BYTES = 16 << 20
 
 
 class TenoError(RuntimeError):
@@ -62,6 +64,7 @@ _SIGS = {
     "teno_workspace_bytes": (ctypes.c_size_t, [_P, _P, ctypes.c_int32]),
     "teno_rhs_frozen": (ctypes.c_int, [_P, _P, _P, _P, _P]),
     "teno_step": (ctypes.c_int, [_P, _P, ctypes.c_double]),
+    "teno_step_noalloc": (ctypes.c_int, [_P, _P, _P, ctypes.c_double, _P, _P, _P]),
     "teno_run": (ctypes.c_int, [_P, _P, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
                                 ctypes.POINTER(ctypes.c_int32)]),
     "teno_poll": (ctypes.c_int, [_P]),
@@ -149,6 +152,25 @@ def workspace_bytes(sys, nx, ny=1, dtype=torch.float64, ckpt_every=0, **opts):
     g = Grid(sys, nx, ny, PERIODIC, PERIODIC, F64 if dtype == torch.float64 else F32, 0.0, 1.0, 0.0, 1.0)
     o = make_opts(**opts)
     return lib().teno_workspace_bytes(ctypes.byref(g), ctypes.byref(o), int(ckpt_every))
+
+
+def step_noalloc(grid, opts, U, dt=0.0, status=None, dt_out=None):
+    """teno_step_noalloc: one SSP-RK3 step of U in place on the current stream, without a context and
+    without any device allocation (fixed scratch of NOALLOC_SCRATCH_BYTES per GPU). grid/opts: Grid
+    and Opts structures (e.g. a Solver's .grid and .opts). status (int32, 1 element) and dt_out
+    (float64, 1 element): optional device outputs."""
+    dt_type = torch.float64 if grid.dtype == F64 else torch.float32
+    nv = NVAR[grid.sys]
+    if not (isinstance(U, torch.Tensor) and U.is_cuda and U.is_contiguous() and U.dtype == dt_type
+            and tuple(U.shape) == (nv, grid.ny, grid.nx)):
+        raise ValueError(f"state must be a contiguous {dt_type} CUDA tensor of shape {(nv, grid.ny, grid.nx)}")
+    if status is not None:
+        _buf(status, (torch.int32,), 1, "status")
+    if dt_out is not None:
+        _buf(dt_out, (torch.float64,), 1, "dt_out")
+    _check(lib().teno_step_noalloc(ctypes.byref(grid), ctypes.byref(opts), _ptr(U), float(dt), _stream(),
+                                   _ptr(status), _ptr(dt_out)), "teno_step_noalloc")
+    return U
 
 
 class Solver:
