@@ -146,22 +146,22 @@ __device__ __forceinline__ SweepArgs<T> item_args(const BatchSweep<T> &b, const 
 // instance's next ring slot. The grid is exactly the item range [begin, end).
 // PACK: tail items, each the ragged last segments of NSEG x P lines of one instance (P per wave).
 template <typename T, int SYS, int DIR, int NSEG, bool PACK>
-__global__ void __launch_bounds__(BLOCK, DIR == 0 ? TENO_MIN_WAVES_X : TENO_MIN_WAVES_Y)
+__global__ void __launch_bounds__(BLOCK, (sweep_min_waves<SYS, DIR, false, DIR == 0 ? MODE_STAGE : MODE_RHS>()))
     batch_sweep_kernel(BatchSweep<T> b)
 {
     constexpr int MODE = DIR == 0 ? MODE_STAGE : MODE_RHS;
+    constexpr bool CG = coef_global<DIR, MODE>();
     __shared__ T rec[rec_size<SYS, DIR, NSEG, PACK>()];
     __shared__ __align__(16) T ext[ext_size<T, SYS, DIR, NSEG, MODE>()];
-    __shared__ T coef[NCOEF_ROWS * 8];
-    __shared__ double red[BLOCK / WAVE * 9];
+    __shared__ T coef_lds[CG ? 1 : NCOEF_ROWS * 8];
     const Item item = b.items[b.begin + xcd_tile(blockIdx.x, gridDim.x)];
     const BatchInst I = b.inst[item.inst];
-    const SweepArgs<T> a = item_args<T, SYS, DIR>(b, I, item.inst);
-    const bool wave0 = __builtin_amdgcn_readfirstlane(threadIdx.x) < WAVE;   // wave-uniform
-    fill_coef(coef);
-    if (MODE == MODE_STAGE && threadIdx.x < BLOCK / WAVE * 9) red[threadIdx.x] = 0.0;   // ordered by the
-    sweep_tile<T, SYS, DIR, false, NSEG, MODE, PACK>(a, item.tile, rec, ext, coef, red);  // tile's first barrier
-    if (MODE == MODE_STAGE) flush_block_maxima(red, &b.ictrl[item.inst].part[b.ring_next][blockIdx.x % NCOPY_B][0], wave0);
+    SweepArgs<T> a = item_args<T, SYS, DIR>(b, I, item.inst);
+    // the x-sweep's wave-speed maxima go to one spread copy of the instance's next ring slot
+    if constexpr (MODE == MODE_STAGE) a.part = &b.ictrl[item.inst].part[b.ring_next][blockIdx.x % NCOPY_B][0];
+    if constexpr (!CG) fill_coef(coef_lds);                 // (ordered by the tile's first barrier)
+    const T *coef = CG ? coef_table<T>() : coef_lds;
+    sweep_tile<T, SYS, DIR, false, NSEG, MODE, PACK>(a, item.tile, rec, ext, coef);
 }
 
 // Wave-speed maxima of every instance of a packed state (items: (instance, chunk of WS_CHUNK cells)).

@@ -25,6 +25,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+
 namespace teno {
 
 // Multiply-adds are fused only within one expression, as written (no fusion across statements): the
@@ -866,13 +867,12 @@ template <typename T> __device__ __forceinline__ void fill_coef(T *coef)
 
 // One tile of a sweep: NSEG line segments staged together in LDS. `tile` enumerates the tiles of
 // the sweep (x: NSEG consecutive segments of the row-major segment list; y: NSEG adjacent columns
-// at one segment position). rec/coef/red: the block's LDS; MODE_STAGE accumulates the wave-speed
-// maxima of the produced cells into red (per-wave slots).
+// at one segment position). rec/ext: the block's LDS; coef: the coefficient rows (LDS or global);
+// MODE_STAGE puts the wave-speed maxima of the produced cells into a.part, the block's spread copy.
 // ext (x-sweeps with an RK stage or a y-part): LDS for the epilogue operands of the owned cells,
 // [NSEG][2][NV][WAVE] (U^n, then the y-part of dU/dt), loaded with the tile.
 template <typename T, int SYS, int DIR, bool FROZEN, int NSEG, int MODE, bool PACK = false>
-__device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *rec, T *ext, const T *coef,
-                                           double *red)
+__device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *rec, T *ext, const T *coef)
 {
     static_assert(!PACK || (SYS == EULER2D && !FROZEN && MODE != MODE_FACES),
                   "packed ragged segments: 2D Euler sweeps without recorded selections");
@@ -1453,8 +1453,12 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
                     m = fmax(m, dpp_shift_z<0x114>(m));  // row_shr:4
                     if (j == 7 && u < NU) {
                         const int q = (int)((SpeedWords<NV>::pack() >> (4 * u)) & 15u);   // word of slot u
-                        red[wid * 9 + q] = fmax(red[wid * 9 + q], m);
-                        if (NV == 4 && (q == 1 || q == 5)) red[wid * 9 + q + 1] = fmax(red[wid * 9 + q + 1], m);
+                        // each wave puts its maxima straight into the block's spread copy (a.part): no
+                        // LDS slots and no barrier at the block's end (a maximum of non-negative doubles
+                        // is the maximum of their bit patterns)
+                        const unsigned long long mb = (unsigned long long)__double_as_longlong(m);
+                        atomicMax(a.part + q, mb);
+                        if (NV == 4 && (q == 1 || q == 5)) atomicMax(a.part + q + 1, mb);
                     }
                 } else {
                     // the words reduced side by side so that their cross-lane steps interleave
@@ -1479,8 +1483,9 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
                         if (!SpeedWords<NV>::use(q)) continue;
                         const double m = __longlong_as_double((long long)(((unsigned long long)mh[q] << 32) | ml[q]));
                         if (k == 0) {
-                            red[wid * 9 + q] = fmax(red[wid * 9 + q], m);
-                            if (NV == 4 && (q == 1 || q == 5)) red[wid * 9 + q + 1] = fmax(red[wid * 9 + q + 1], m);
+                            const unsigned long long mb = (unsigned long long)__double_as_longlong(m);
+                            atomicMax(a.part + q, mb);
+                            if (NV == 4 && (q == 1 || q == 5)) atomicMax(a.part + q + 1, mb);
                         }
                     }
                 }
@@ -1528,22 +1533,6 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
     if (bad) atomicOr(a.err, bad);
 }
 
-// End of a MODE_STAGE block: the per-wave maxima slots reduced by lanes 0..8 of wave 0, one atomic
-// maximum per word into one spread copy. wave0 is wave-uniform and the lane number is recomputed, so
-// no thread index has to stay live through the tile.
-__device__ __forceinline__ void flush_block_maxima(const double *red, unsigned long long *copy, bool wave0)
-{
-    __syncthreads();
-    if (wave0) {
-        const int t = lane_id_now();
-        if (t < 9) {
-            double m = 0.0;
-            for (int q = 0; q < BLOCK / WAVE; ++q) m = fmax(m, red[q * 9 + t]);
-            atomicMax(copy + t, (unsigned long long)__double_as_longlong(m));
-        }
-    }
-}
-
 // Workgroups of a launch are handed to the 8 XCDs round-robin (block b to XCD b mod 8), and each
 // XCD has its own L2. Renumber so that every XCD walks a contiguous range of tiles in order:
 // neighbouring tiles, which share cache lines and halo cells, then meet in the same L2. A bijection
@@ -1566,8 +1555,19 @@ template <typename T, int SYS, int DIR, int NSEG, int MODE> constexpr int ext_si
 // scheduled blocks overlap their staging with the compute of resident ones).
 // REC = false: no selection masks or flags are written (the pointers are known null at compile
 // time, so the mask words are not assembled at all).
+// Minimum waves per SIMD of a sweep kernel's register budget.
+template <int SYS, int DIR, bool FROZEN, int MODE> constexpr int sweep_min_waves()
+{
+    return (SYS == EULER1D && FROZEN) ? 3 : (DIR == 0 ? TENO_MIN_WAVES_X : TENO_MIN_WAVES_Y);
+}
+
+// x-sweep stage kernels read the coefficient rows (needed only where a face cuts a stencil) from the
+// global table instead of copying it into LDS first (with the maxima posted per wave, 2.5 % faster on
+// the 4096^2 benchmark state).
+template <int DIR, int MODE> constexpr bool coef_global() { return DIR == 0 && MODE == MODE_STAGE; }
+
 template <typename T, int SYS, int DIR, bool FROZEN, int MODE, bool REC = true>
-__global__ void __launch_bounds__(BLOCK, (SYS == EULER1D && FROZEN) ? 3 : (DIR == 0 ? TENO_MIN_WAVES_X : TENO_MIN_WAVES_Y))
+__global__ void __launch_bounds__(BLOCK, (sweep_min_waves<SYS, DIR, FROZEN, MODE>()))
     sweep_kernel(SweepArgs<T> a)
 {
     if constexpr (!REC) {
@@ -1575,16 +1575,14 @@ __global__ void __launch_bounds__(BLOCK, (SYS == EULER1D && FROZEN) ? 3 : (DIR =
         a.flags_out = nullptr;
     }
     constexpr int NSEG = DIR == 0 ? NSEG_X : NSEG_Y;
+    constexpr bool CG = coef_global<DIR, MODE>();
     __shared__ T rec[rec_size<SYS, DIR, NSEG, false>()];
     __shared__ __align__(16) T ext[ext_size<T, SYS, DIR, NSEG, MODE>()];
-    __shared__ T coef[NCOEF_ROWS * 8];
-    __shared__ double red[BLOCK / WAVE * 9];
-    const bool wave0 = __builtin_amdgcn_readfirstlane(threadIdx.x) < WAVE;   // wave-uniform
-    fill_coef(coef);
-    if (MODE == MODE_STAGE && threadIdx.x < BLOCK / WAVE * 9) red[threadIdx.x] = 0.0;   // ordered by the
-    sweep_tile<T, SYS, DIR, FROZEN, NSEG, MODE>(a, xcd_tile(blockIdx.x, gridDim.x), rec, ext, coef,
-                                                red);                                     // tile's first barrier
-    if (MODE == MODE_STAGE) flush_block_maxima(red, a.part + (size_t)(blockIdx.x % NCOPY) * NWORD, wave0);
+    __shared__ T coef_lds[CG ? 1 : NCOEF_ROWS * 8];
+    if constexpr (!CG) fill_coef(coef_lds);                 // (ordered by the tile's first barrier)
+    const T *coef = CG ? coef_table<T>() : coef_lds;
+    if constexpr (MODE == MODE_STAGE) a.part += (size_t)(blockIdx.x % NCOPY) * NWORD;   // the block's copy
+    sweep_tile<T, SYS, DIR, FROZEN, NSEG, MODE>(a, xcd_tile(blockIdx.x, gridDim.x), rec, ext, coef);
 }
 
 // ------------------------------------------------------------------------------------------------
