@@ -377,6 +377,9 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-extras", action="store_true", help="skip the batched and adjoint side runs")
+    ap.add_argument("--only", choices=["batch", "adjoint"], default=None,
+                    help="run only that side leg and print its result (for profiling)")
+    ap.add_argument("--adjoint-steps", type=int, default=400, help="steps of the adjoint leg")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="after the timed region, one plain device-to-device copy of this many bytes "
                          "(a reference kernel for calibrating profiler byte counters)")
@@ -391,6 +394,12 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.only == "batch":
+        print(json.dumps(batched_speedup()), flush=True)
+        return
+    if args.only == "adjoint":
+        print(json.dumps(adjoint_cost(nsteps=args.adjoint_steps)), flush=True)
+        return
     n = args.n
     log(f"building the 2D Euler {n}x{n} state")
     pr = W.euler2d(args.seed, n=n, nsteps=args.steps)
@@ -514,8 +523,8 @@ def main():
         out["scheme_cost"] = scheme_cost(n=n)
         log(json.dumps(out["scheme_cost"]))
         torch.cuda.empty_cache()
-        log("adjoint cost (1024^2, 400 steps, checkpoints every 20)")
-        out["adjoint"] = adjoint_cost()
+        log(f"adjoint cost (1024^2, {args.adjoint_steps} steps, checkpoints every 20)")
+        out["adjoint"] = adjoint_cost(nsteps=args.adjoint_steps)
         log(json.dumps(out["adjoint"]))
         torch.cuda.empty_cache()
     if not args.no_cpu:

@@ -27,6 +27,7 @@
 #include "teno.h"
 #include "teno_device.hpp"
 #include "teno_internal.hpp"
+#include "teno_worklist.hpp"
 
 using namespace teno;
 
@@ -81,17 +82,7 @@ template <typename T> struct BatchSweep {
     int characteristic;             // 0: reconstruction per conserved component
 };
 
-int nseg_of(int len) { return (len + SEG_CELLS - 1) / SEG_CELLS; }
-
-// Whether a 2D instance's ragged last segments along a sweep (line length len, nlines lines) are
-// packed several lines to a wave: at least two pieces fit and there are lines to share a wave.
-__host__ __device__ inline bool packable(int len, int nlines) { return nlines > 1 && tail_geom(len).P >= 2; }
-
-int tiles_x(const teno_grid &g, int nseg_x)
-{
-    long long segs = (long long)nseg_of(g.nx) * g.ny;
-    return (int)((segs + nseg_x - 1) / nseg_x);
-}
+int tiles_x(const teno_grid &g, int nseg_x) { return (int)x_main_items(g.nx, g.ny, nseg_x, false); }
 
 }  // namespace
 
@@ -117,8 +108,7 @@ __device__ __forceinline__ SweepArgs<T> item_args(const BatchSweep<T> &b, const 
     a.ny = I.ny;
     a.len = DIR == 0 ? I.nx : I.ny;
     a.nlines = DIR == 0 ? I.ny : I.nx;
-    a.nseg = (a.len + SEG_CELLS - 1) / SEG_CELLS;
-    if (b.packed && (DIR == 0 ? I.pack_x : I.pack_y)) a.nseg -= 1;   // the last one is a tail item's
+    a.nseg = main_nseg(a.len, b.packed && (DIR == 0 ? I.pack_x : I.pack_y));   // (packed: the last is a tail item's)
     a.bc = DIR == 0 ? I.bc_x : I.bc_y;
     a.bc_other = 0;
     a.mode = b.mode;
@@ -150,7 +140,9 @@ __global__ void __launch_bounds__(BLOCK, (sweep_min_waves<SYS, DIR, false, DIR =
     batch_sweep_kernel(BatchSweep<T> b)
 {
     constexpr int MODE = DIR == 0 ? MODE_STAGE : MODE_RHS;
-    constexpr bool CG = coef_global<DIR, MODE>();
+    // (the coefficient rows stay in LDS here: the mixture's small instances cut many stencils, and
+    // reading the rows from global memory measured 2 % slower on the 512-instance batch)
+    constexpr bool CG = false;
     __shared__ T rec[rec_size<SYS, DIR, NSEG, PACK>()];
     __shared__ __align__(16) T ext[ext_size<T, SYS, DIR, NSEG, MODE>()];
     __shared__ T coef_lds[CG ? 1 : NCOEF_ROWS * 8];
@@ -588,8 +580,7 @@ teno_status teno_batch_create(const teno_grid *grids, int32_t n, const teno_opts
             for (int k = 0; k < n; ++k) {                       // 2D main items
                 if (grids[k].sys != TENO_EULER2D) continue;
                 const bool pk = p == 1 && b->inst[k].pack_x;
-                const long long segs = (long long)(nseg_of(grids[k].nx) - (pk ? 1 : 0)) * grids[k].ny;
-                const int t = (int)((segs + ns - 1) / ns);
+                const int t = (int)x_main_items(grids[k].nx, grids[k].ny, ns, pk);
                 if (p == 0) b->xb[v][k] = (int)it.size();
                 for (int q = 0; q < t; ++q) it.push_back({k, q});
                 if (p == 0) b->xe[v][k] = (int)it.size();
@@ -597,8 +588,7 @@ teno_status teno_batch_create(const teno_grid *grids, int32_t n, const teno_opts
             b->x2m_end[v][p] = (int)it.size();
             for (int k = 0; k < n && p == 1; ++k) {             // 2D tail items
                 if (grids[k].sys != TENO_EULER2D || !b->inst[k].pack_x) continue;
-                const int per = ns * tail_geom(grids[k].nx).P;   // lines per tail item
-                const int t = (grids[k].ny + per - 1) / per;
+                const int t = (int)x_tail_items(grids[k].nx, grids[k].ny, ns);
                 for (int q = 0; q < t; ++q) it.push_back({k, q});
             }
             b->x2_end[v][p] = (int)it.size();
@@ -619,7 +609,7 @@ teno_status teno_batch_create(const teno_grid *grids, int32_t n, const teno_opts
                 if (p == 0) b->yb[v][k] = (int)it.size();
                 if (grids[k].sys == TENO_EULER2D) {
                     const bool pk = p == 1 && b->inst[k].pack_y;
-                    const int t = ((grids[k].nx + ns - 1) / ns) * (nseg_of(grids[k].ny) - (pk ? 1 : 0));
+                    const int t = (int)y_main_items(grids[k].nx, grids[k].ny, ns, pk);
                     for (int q = 0; q < t; ++q) it.push_back({k, q});
                 }
                 if (p == 0) b->ye[v][k] = (int)it.size();
@@ -627,8 +617,7 @@ teno_status teno_batch_create(const teno_grid *grids, int32_t n, const teno_opts
             b->ym_end[v][p] = (int)it.size();
             for (int k = 0; k < n && p == 1; ++k) {             // y tail items
                 if (grids[k].sys != TENO_EULER2D || !b->inst[k].pack_y) continue;
-                const int per = ns * tail_geom(grids[k].ny).P;
-                const int t = (grids[k].nx + per - 1) / per;
+                const int t = (int)y_tail_items(grids[k].nx, grids[k].ny, ns);
                 for (int q = 0; q < t; ++q) it.push_back({k, q});
             }
             b->y_total[v][p] = (int)it.size();

@@ -64,6 +64,50 @@ __host__ __device__ inline TailGeom tail_geom(int len)
     g.P = PACK_SPAN / g.W;
     return g;
 }
+// Segment s of a sweep's tile `tile` (nseg_tile segments per tile): its line (-1: none) and first
+// cell. x-sweeps: consecutive segments of the row-major list of nseg segments per line; y-sweeps:
+// nseg_tile adjacent lines at one segment position. (Index maps shared by the kernels and the host.)
+__host__ __device__ inline void tile_segment(int dir, int nseg_tile, int tile, int s, int nseg, int nlines, int &line,
+                                             int &c0)
+{
+    if (dir == 0) {
+        const int id = tile * nseg_tile + s;
+        line = id / nseg;
+        c0 = (id % nseg) * SEG_CELLS;
+    } else {
+        const int ntile = (nlines + nseg_tile - 1) / nseg_tile;
+        line = (tile % ntile) * nseg_tile + s;
+        c0 = (tile / ntile) * SEG_CELLS;
+    }
+    if (line >= nlines) line = -1;
+}
+
+// A tail tile: the ragged last segments of nseg_tile x P lines starting at line l0; M makes
+// (k M) >> 16 the exact quotient k / W for 0 <= k < 72 (checked on the host for every W).
+struct PackMap {
+    int c0, nt, W, P, M, l0;
+};
+__host__ __device__ inline PackMap pack_map(int len, int tile, int nseg_tile)
+{
+    const TailGeom g = tail_geom(len);
+    PackMap m;
+    m.c0 = g.c0;
+    m.nt = g.nt;
+    m.W = g.W;
+    m.P = g.P;
+    m.M = 65536 / g.W + 1;
+    m.l0 = tile * nseg_tile * g.P;
+    return m;
+}
+// The piece that lane (or staged position) k < 72 of a segment slot belongs to.
+__host__ __device__ inline int pack_piece(const PackMap &m, int k) { return (k * m.M) >> 16; }
+// The line of piece i of segment slot s, or -1 past the tile's pieces or the instance's lines.
+__host__ __device__ inline int pack_line(const PackMap &m, int i, int s, int nseg_tile, int nlines)
+{
+    const int line = m.l0 + i * nseg_tile + s;
+    return (i < m.P && line < nlines) ? line : -1;
+}
+
 #ifndef TENO_NSEG_X
 #define TENO_NSEG_X 4
 #endif
@@ -122,7 +166,7 @@ template <int SYS, int DIR> __device__ __forceinline__ constexpr int gvar(int v)
     return (SYS == EULER2D && DIR == 1 && (v == 1 || v == 2)) ? 3 - v : v;
 }
 
-__device__ __forceinline__ int bc_index(int i, int n, int bc)
+__host__ __device__ inline int bc_index(int i, int n, int bc)
 {
     if (bc == 0) {
         i %= n;
@@ -194,7 +238,7 @@ __device__ __forceinline__ double uniform_f64(double x)
 __device__ __forceinline__ void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
 // bc_index for -n <= i < 2n (one wrap at most, no division).
-__device__ __forceinline__ int bc_index_near(int i, int n, int bc)
+__host__ __device__ inline int bc_index_near(int i, int n, int bc)
 {
     if (bc == 0) return i < 0 ? i + n : (i >= n ? i - n : i);
     return i < 0 ? 0 : (i >= n ? n - 1 : i);
@@ -886,33 +930,12 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
     const size_t ncell = (size_t)a.nx * a.ny;
 
     // segment s of this block -> (line, c0); line < 0 marks an empty slot
-    auto seg_of = [&](int s, int &line, int &c0) {
-        if (DIR == 0) {
-            int id = tile * NSEG + s;
-            line = id / a.nseg;
-            c0 = (id % a.nseg) * SEG_CELLS;
-            if (line >= a.nlines) line = -1;
-        } else {
-            int ntile = (a.nlines + NSEG - 1) / NSEG;
-            int pos = tile / ntile;
-            line = (tile % ntile) * NSEG + s;
-            c0 = pos * SEG_CELLS;
-            if (line >= a.nlines) line = -1;
-        }
-    };
+    auto seg_of = [&](int s, int &line, int &c0) { tile_segment(DIR, NSEG, tile, s, a.nseg, a.nlines, line, c0); };
 
-    // packed ragged segments (PACK): the tile's lines start at pk_l0; piece i of segment s is line
-    // pk_l0 + i NSEG + s; lane k belongs to piece (k pk_M) >> 16 (exact division by W for k < 72)
-    int pk_c0 = 0, pk_nt = 0, pk_W = 1, pk_P = 1, pk_M = 0, pk_l0 = 0;
-    if constexpr (PACK) {
-        const TailGeom tg = tail_geom(a.len);
-        pk_c0 = tg.c0;
-        pk_nt = tg.nt;
-        pk_W = tg.W;
-        pk_P = tg.P;
-        pk_M = 65536 / pk_W + 1;
-        pk_l0 = tile * NSEG * pk_P;
-    }
+    // packed ragged segments (PACK): the tile's lines start at pm.l0; piece i of segment s is line
+    // pm.l0 + i NSEG + s; lane k belongs to piece pack_piece(pm, k)
+    PackMap pm{0, 0, 1, 1, 0, 0};
+    if constexpr (PACK) pm = pack_map(a.len, tile, NSEG);
 
     // Lax-Friedrichs constants of this direction and the stage's dt, read before any background copy
     // is issued (vector-memory completions are waited for in order) and kept in scalar registers
@@ -986,7 +1009,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
     constexpr bool HAS_EXT = DIR == 0 && MODE != MODE_FACES && !PACK;
     if constexpr (PACK && DIR == 0) {
         for (int s = __builtin_amdgcn_readfirstlane(wid); s < NSEG; s += BLOCK / WAVE) {
-            const int line0 = pk_l0 + s;                 // piece 0: the wave has no line if absent
+            const int line0 = pm.l0 + s;                 // piece 0: the wave has no line if absent
             if (line0 >= a.nlines) continue;             // wave-uniform
             constexpr int IT = (SEG_LOAD + WAVE - 1) / WAVE;        // loads first, then conversions
             T uc[IT][NV];
@@ -994,11 +1017,11 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
             for (int it = 0; it < IT; ++it) {
                 const int q = lane + it * WAVE;
                 if (q < SEG_LOAD) {
-                    const int i = (q * pk_M) >> 16, ql = q - i * pk_W;
-                    int line = pk_l0 + i * NSEG + s;
-                    if (i >= pk_P || line >= a.nlines) line = line0;   // idle positions: any valid cell
-                    const int g = near ? bc_index_near(pk_c0 - SEG_HALO + ql, a.len, a.bc)
-                                       : bc_index(pk_c0 - SEG_HALO + ql, a.len, a.bc);
+                    const int i = pack_piece(pm, q), ql = q - i * pm.W;
+                    int line = pack_line(pm, i, s, NSEG, a.nlines);
+                    if (line < 0) line = line0;                 // idle positions: any valid cell
+                    const int g = near ? bc_index_near(pm.c0 - SEG_HALO + ql, a.len, a.bc)
+                                       : bc_index(pm.c0 - SEG_HALO + ql, a.len, a.bc);
                     load_cell((size_t)line * a.nx + g, uc[it]);
                 }
             }
@@ -1016,13 +1039,13 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
             pos[it] = -1;
             if (idx < NCELL) {
                 const int s = idx % NSEG, q = idx / NSEG;
-                const int line0 = pk_l0 + s;
+                const int line0 = pm.l0 + s;
                 if (line0 < a.nlines) {
-                    const int i = (q * pk_M) >> 16, ql = q - i * pk_W;
-                    int line = pk_l0 + i * NSEG + s;
-                    if (i >= pk_P || line >= a.nlines) line = line0;
-                    const int g = near ? bc_index_near(pk_c0 - SEG_HALO + ql, a.len, a.bc)
-                                       : bc_index(pk_c0 - SEG_HALO + ql, a.len, a.bc);
+                    const int i = pack_piece(pm, q), ql = q - i * pm.W;
+                    int line = pack_line(pm, i, s, NSEG, a.nlines);
+                    if (line < 0) line = line0;
+                    const int g = near ? bc_index_near(pm.c0 - SEG_HALO + ql, a.len, a.bc)
+                                       : bc_index(pm.c0 - SEG_HALO + ql, a.len, a.bc);
                     pos[it] = s * SEG_STRIDE + q;
                     load_cell((size_t)g * a.nx + line, uc[it]);
                 }
@@ -1127,8 +1150,8 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
     for (int s = __builtin_amdgcn_readfirstlane(wid); s < NSEG; s += BLOCK / WAVE) {
         int line, c0;
         if constexpr (PACK) {
-            line = pk_l0 + s;
-            c0 = pk_c0;
+            line = pm.l0 + s;
+            c0 = pm.c0;
             if (line >= a.nlines) continue;     // wave-uniform
         } else {
             seg_of(s, line, c0);
@@ -1137,13 +1160,12 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
         const T *R0 = rec + s * segoff;
         const int k = lane_id_now();
         // this lane's line and position in it (packed: its piece's line and the lane within the piece)
-        int kl = k, lline = line;
+        int kl = k;
         bool needed = true;                     // the lane's face or its flags are used
         if constexpr (PACK) {
-            const int i = (k * pk_M) >> 16;
-            kl = k - i * pk_W;
-            lline = pk_l0 + i * NSEG + s;
-            needed = i < pk_P && lline < a.nlines && kl <= pk_nt + 2;
+            const int i = pack_piece(pm, k);
+            kl = k - i * pm.W;
+            needed = pack_line(pm, i, s, NSEG, a.nlines) >= 0 && kl <= pm.nt + 2;
         }
         const int f = c0 - 1 + kl;              // this lane's face
         bool face_ok = needed && kl >= 1 && kl <= 62 && f <= a.len;
@@ -1334,10 +1356,10 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
             asm volatile("" ::: "memory");      // orders the record reads before the epilogue
             bool pv = true;
             if constexpr (PACK) {
-                const int i = (kk * pk_M) >> 16;
-                eline = pk_l0 + i * NSEG + s;
-                pv = i < pk_P && eline < a.nlines;
-                kk -= i * pk_W;
+                const int i = pack_piece(pm, kk);
+                eline = pack_line(pm, i, s, NSEG, a.nlines);
+                pv = eline >= 0;
+                kk -= i * pm.W;
             }
             fe = c0 - 1 + kk;
             face_ok = pv && kk >= 1 && kk <= 62 && fe <= a.len;
@@ -1496,10 +1518,10 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
         __syncthreads();
         for (int idx = tid; idx < NV * WAVE * NSEG; idx += BLOCK) {
             const int sg = idx % NSEG, kk = (idx / NSEG) % WAVE, v = idx / (NSEG * WAVE);
-            const int i = ((kk + 1) * pk_M) >> 16, kl = kk + 1 - i * pk_W;   // lane kk + 1
-            const int line = pk_l0 + i * NSEG + sg;
-            if (i >= pk_P || line >= a.nlines || kl < 1 || kl > pk_nt) continue;
-            a.out[(size_t)gvar<SYS, DIR>(v) * ncell + (size_t)(pk_c0 + kl - 1) * a.nx + line] =
+            const int i = pack_piece(pm, kk + 1), kl = kk + 1 - i * pm.W;   // lane kk + 1
+            const int line = pack_line(pm, i, sg, NSEG, a.nlines);
+            if (line < 0 || kl < 1 || kl > pm.nt) continue;
+            a.out[(size_t)gvar<SYS, DIR>(v) * ncell + (size_t)(pm.c0 + kl - 1) * a.nx + line] =
                 rec[sg * SEG_STRIDE + v * WAVE + kk];
         }
     } else if constexpr (STAGE_OUT) {
