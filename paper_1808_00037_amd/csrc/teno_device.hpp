@@ -492,20 +492,24 @@ template <typename T> __device__ __forceinline__ T fast_sqrt(T x)
     return s;
 }
 
-// r^q for the exponent q of eq:TENO1: ((r r) r)^2 for the paper's q = 6, else q - 1 products.
-template <typename T> __device__ __forceinline__ T pow_q(T r, int q)
+// r^q for the exponent q of eq:TENO1. QC = 6: the paper's q = 6 fixed at compile time, ((r r) r)^2;
+// QC = 0: q taken at run time, q - 1 products (for q = 6 the same products in the same order).
+template <int QC, typename T> __device__ __forceinline__ T pow_q(T r, int q)
 {
-    if (q == 6) {
+    if constexpr (QC == 6) {
         T g = r * r * r;
         return g * g;
+    } else {
+        if (q == 6) return pow_q<6>(r, 6);
+        T g = r;
+        for (int j = 1; j < q; ++j) g *= r;
+        return g;
     }
-    T g = r;
-    for (int j = 1; j < q; ++j) g *= r;
-    return g;
 }
 
 // gamma_k = (C + tau5 / (beta_k + eps))^q of the three substencils, up to one common positive factor
 // (the cut-off and chi only use their ratios).
+template <int QC>
 __device__ __forceinline__ void gamma3(const Smooth<double> &m, double eps4, double C, int q, double g[3])
 {
     double D0 = m.b0 + eps4, D1 = m.b1 + eps4, D2 = m.b2 + eps4;
@@ -514,26 +518,27 @@ __device__ __forceinline__ void gamma3(const Smooth<double> &m, double eps4, dou
     double r0 = C + tinv * (D1 * D2);
     double r1 = C + tinv * (D0 * D2);
     double r2 = C + tinv * D01;
-    g[0] = pow_q(r0, q);
-    g[1] = pow_q(r1, q);
-    g[2] = pow_q(r2, q);
+    g[0] = pow_q<QC>(r0, q);
+    g[1] = pow_q<QC>(r1, q);
+    g[2] = pow_q<QC>(r2, q);
 }
 
 // Single precision: gamma_k / gamma_max keeps every term in [0, 1] (no overflow of r^q).
+template <int QC>
 __device__ __forceinline__ void gamma3(const Smooth<float> &m, float eps4, float C, int q, float g[3])
 {
     float r0 = C + m.tau / (m.b0 + eps4), r1 = C + m.tau / (m.b1 + eps4), r2 = C + m.tau / (m.b2 + eps4);
     float rm = fmaxf(r0, fmaxf(r1, r2));
-    g[0] = pow_q(r0 / rm, q);
-    g[1] = pow_q(r1 / rm, q);
-    g[2] = pow_q(r2 / rm, q);
+    g[0] = pow_q<QC>(r0 / rm, q);
+    g[1] = pow_q<QC>(r1 / rm, q);
+    g[2] = pow_q<QC>(r2 / rm, q);
 }
 
-template <typename T>
+template <int QC, typename T>
 __device__ __forceinline__ unsigned cutoff3(const Smooth<T> &m, T eps4, T ct, T C, int q)
 {
     T g[3];
-    gamma3(m, eps4, C, q, g);
+    gamma3<QC>(m, eps4, C, q, g);
     T thr = ct * ((g[0] + g[1]) + g[2]);
     return (g[0] < thr ? 0u : 1u) | (g[1] < thr ? 0u : 2u) | (g[2] < thr ? 0u : 4u);
 }
@@ -543,7 +548,7 @@ template <typename T>
 __device__ __forceinline__ void chi3(const Smooth<T> &m, T eps4, T C, int q, T chi[3])
 {
     T g[3];
-    gamma3(m, eps4, C, q, g);
+    gamma3<0>(m, eps4, C, q, g);
     const T s = (g[0] + g[1]) + g[2];
     chi[0] = g[0] / s;
     chi[1] = g[1] / s;
@@ -1288,7 +1293,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
                 // (lanes of a packed wave that no piece needs count as smooth: their stencils straddle
                 // two lines)
                 // (both sides evaluated, without a branch between them)
-                const bool easy = (all_smooth(sp, a.smooth_k, a.keps4) & all_smooth(sm, a.smooth_k, a.keps4)) | !needed;
+                const bool easy = ((int)all_smooth(sp, a.smooth_k, a.keps4) & (int)all_smooth(sm, a.smooth_k, a.keps4)) | !needed;
                 if (__all(easy)) {
                     // every flag of every face of the wave is 1: the full stencil on both sides
                     fword |= 63u << (6 * sf);
@@ -1299,8 +1304,18 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
                         mp = mm = TENO5_ROW[7];
                     }
                 } else {
-                    unsigned dp = easy ? 7u : cutoff3(sp, a.eps4, a.ct, a.C, a.q);
-                    unsigned dm = easy ? 7u : cutoff3(sm, a.eps4, a.ct, a.C, a.q);
+                    // both sides of the lanes off the shortcut in one branch, the paper's exponent
+                    // as a constant (any other q at run time)
+                    unsigned dp = 7u, dm = 7u;
+                    if (!easy) {
+                        if (a.q == 6) {
+                            dp = cutoff3<6>(sp, a.eps4, a.ct, a.C, 6);
+                            dm = cutoff3<6>(sm, a.eps4, a.ct, a.C, 6);
+                        } else {
+                            dp = cutoff3<0>(sp, a.eps4, a.ct, a.C, a.q);
+                            dm = cutoff3<0>(sm, a.eps4, a.ct, a.C, a.q);
+                        }
+                    }
                     unsigned bits = dp | (dm << 3);
                     fword |= bits << (6 * sf);
                     if (a.scheme == 0) {
