@@ -195,8 +195,9 @@ def cpu_leg(problem, gpu, threads, budget_s=6.0):
 
 def batched_speedup(seed=3, nsteps=20):
     """512 Euler instances (256 1D, N log-uniform in [256, 65536]; 256 2D squares, side log-uniform in
-    [64, 1024]) advanced nsteps SSP-RK3 steps: one persistent graph-captured launch sequence (mode 0,
-    autotuned tiles) vs one launch per instance per kernel (mode 1); states must be bitwise equal."""
+    [64, 1024]) advanced nsteps SSP-RK3 steps: one graph of static work-list launches over all
+    instances (mode 0, autotuned tiles) vs one launch per instance per kernel (mode 1); states must
+    be bitwise equal."""
     import torch
     from paper_1808_00037_amd import teno as T
     from paper_1808_00037_amd import workloads as W

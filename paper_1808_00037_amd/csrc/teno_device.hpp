@@ -673,7 +673,7 @@ template <typename T> struct SweepArgs {
     int nx, ny;                 // grid
     int len, nlines;            // cells per line along the sweep, number of lines
     int nseg;                   // segments per line
-    int ntiles;                 // tiles of the sweep (persistent launches loop over them)
+    int ntiles;                 // tiles of the sweep (one block each)
     int bc;                     // boundary condition along the sweep
     int bc_other;               // (unused by the sweep itself)
     int mode, stage, scheme, alpha_mode;
@@ -1588,10 +1588,6 @@ template <typename T, int SYS, int DIR, int NSEG, int MODE> constexpr int ext_si
     return (DIR == 0 && MODE != MODE_FACES) ? NSEG * 2 * Sys<SYS>::NV * WAVE + 2 : 1;
 }
 
-// One tile per block (measured faster on MI355X than persistent blocks looping over tiles: freshly
-// scheduled blocks overlap their staging with the compute of resident ones).
-// REC = false: no selection masks or flags are written (the pointers are known null at compile
-// time, so the mask words are not assembled at all).
 // Minimum waves per SIMD of a sweep kernel's register budget.
 template <int SYS, int DIR, bool FROZEN, int MODE> constexpr int sweep_min_waves()
 {
@@ -1603,6 +1599,10 @@ template <int SYS, int DIR, bool FROZEN, int MODE> constexpr int sweep_min_waves
 // the 4096^2 benchmark state).
 template <int DIR, int MODE> constexpr bool coef_global() { return DIR == 0 && MODE == MODE_STAGE; }
 
+// One tile per block (measured faster on MI355X than persistent blocks looping over tiles: freshly
+// scheduled blocks overlap their staging with the compute of resident ones).
+// REC = false: no selection masks or flags are written (the pointers are known null at compile
+// time, so the mask words are not assembled at all).
 template <typename T, int SYS, int DIR, bool FROZEN, int MODE, bool REC = true>
 __global__ void __launch_bounds__(BLOCK, (sweep_min_waves<SYS, DIR, FROZEN, MODE>()))
     sweep_kernel(SweepArgs<T> a)
