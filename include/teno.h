@@ -96,7 +96,7 @@ teno_status teno_probe_fp64_fma(void *stream, int32_t iters, double *tflops);
 /* Device memory, in bytes, that a context for (grid, opts) allocates by itself at most: the control
  * block (at teno_create), the SSP-RK3 stage scratch (two states, plus the y-part of dU/dt for 2D
  * Euler; at the first step), and, when ckpt_every > 0, the scratch of a reverse sweep
- * teno_run_vjp(.., ckpt_every, ..) ((3 ckpt_every + 3) double states). Caller-owned buffers
+ * teno_run_vjp(.., ckpt_every, ..) ((3 ckpt_every + 5) double states). Caller-owned buffers
  * (states, masks, checkpoints) are not included. Returns 0 for an invalid grid or opts. */
 size_t teno_workspace_bytes(const teno_grid *grid, const teno_opts *opts, int32_t ckpt_every);
 
@@ -232,7 +232,8 @@ teno_status teno_run_replay(teno_ctx *ctx, void *U, int32_t nsteps, const uint32
 
 /* Reverse sweep: given lam = dJ/dU(T) in lam_io, overwrite it with dJ/dU(0). Recomputes each
  * checkpoint segment forward (frozen) and applies the adjoint of every RK stage in reverse.
- * Needs masks_dev (recorded). Scratch: 3*ckpt_every+1 states allocated on first use. */
+ * Needs masks_dev (recorded). Scratch: 3*ckpt_every+5 double states, allocated on first use
+ * (the stage states of one segment, the running state, the y part of J^T mu, two mu and one lam). */
 teno_status teno_run_vjp(teno_ctx *ctx, const void *ckpt_dev, const uint32_t *masks_dev,
                          const double *alpha_dt_dev, int32_t nsteps, int32_t ckpt_every, void *lam_io);
 

@@ -5,8 +5,8 @@
 // (written by the stage-preparation kernel on the device).
 // Reverse sweep: per checkpoint segment, in reverse: replay the segment forward with the recorded
 // selection/constants/dt while keeping the three stage inputs of every step, then apply the adjoint
-// of every stage in reverse: G = J^T mu by the vector-Jacobian kernels (y, then x accumulating) and
-// the elementwise stage adjoint.
+// of every stage in reverse: G = J^T mu by the vector-Jacobian kernels (y into a buffer, then x),
+// with the stage adjoint applied to G in the x kernel's epilogue (G itself is never stored).
 #include <hip/hip_runtime.h>
 
 #include <cstring>
@@ -24,9 +24,18 @@ using namespace teno;
         if (e_ != hipSuccess) return TENO_E_HIP;        \
     } while (0)
 
+// Plain product (rk < 0): grad = / += J^T lam. Fused (rk = 0, 1, 2, see VjpArgs): the adjoint of RK stage
+// rk applied to G = gy + this direction's product.
+struct StageIO {
+    int rk = -1;
+    const double *gy = nullptr;
+    double *lam_step = nullptr, *lam_next = nullptr, *mu_next = nullptr;
+    const double *dt = nullptr;
+};
+
 template <int SYS, int DIR>
 static void launch_vjp_t(teno_ctx *c, const double *U, const double *lam, double *grad, const uint32_t *masks,
-                         const double *alpha, int accumulate)
+                         const double *alpha, int accumulate, const StageIO &io = StageIO())
 {
     VjpArgs a;
     std::memset(&a, 0, sizeof a);
@@ -46,6 +55,12 @@ static void launch_vjp_t(teno_ctx *c, const double *U, const double *lam, double
     a.inv_h = 1.0 / (DIR == 0 ? c->dx : c->dy);
     a.gamma = c->opts.gamma;
     a.adv = c->opts.adv_speed;
+    a.rk = io.rk;
+    a.gy = io.gy;
+    a.lam_step = io.lam_step;
+    a.lam_next = io.lam_next;
+    a.mu_next = io.mu_next;
+    a.dt = io.dt;
     unsigned nblocks;
     if (DIR == 0) {
         nblocks = (unsigned)(((size_t)a.nseg * a.nlines + ADJ_NSEG - 1) / ADJ_NSEG);
@@ -70,6 +85,23 @@ static void enqueue_rhs_vjp(teno_ctx *c, const double *U, const uint32_t *masks,
     }
 }
 
+// The adjoint of one RK stage: G = J(U)^T m (the y part into Gy first for 2D), then the stage adjoint
+// in the x kernel's epilogue (io.gy set here).
+static void enqueue_stage_vjp(teno_ctx *c, const double *U, const uint32_t *masks, const double *alpha,
+                              const double *m, double *Gy, StageIO io)
+{
+    switch (c->grid.sys) {
+    case TENO_ADV1D: launch_vjp_t<ADV1D, 0>(c, U, m, nullptr, masks, alpha, 0, io); break;
+    case TENO_BURGERS1D: launch_vjp_t<BURGERS1D, 0>(c, U, m, nullptr, masks, alpha, 0, io); break;
+    case TENO_EULER1D: launch_vjp_t<EULER1D, 0>(c, U, m, nullptr, masks, alpha, 0, io); break;
+    default:
+        launch_vjp_t<EULER2D, 1>(c, U, m, Gy, masks + c->nfx, alpha, 0);
+        io.gy = Gy;
+        launch_vjp_t<EULER2D, 0>(c, U, m, nullptr, masks, alpha, 0, io);
+        break;
+    }
+}
+
 static bool adjoint_supported(const teno_ctx *c)
 {
     if (c->grid.dtype != TENO_F64 || !c->opts.characteristic) return false;
@@ -80,8 +112,9 @@ static bool adjoint_supported(const teno_ctx *c)
 
 static teno_status ensure_adj_scratch(teno_ctx *c, int ckpt_every)
 {
-    // 3 * ckpt_every stage states of one segment, the running state X, mu and G
-    size_t need = ((size_t)3 * (size_t)ckpt_every + 3) * c->nelem * sizeof(double);
+    // 3 * ckpt_every stage states of one segment, the running state X, the y part Gy, two buffers of
+    // mu and a second buffer of lam
+    size_t need = ((size_t)3 * (size_t)ckpt_every + 5) * c->nelem * sizeof(double);
     if (c->adj_scratch && c->adj_scratch_bytes >= need) return TENO_OK;
     if (c->adj_scratch) HIP_TRY(hipFree(c->adj_scratch));
     c->adj_scratch = nullptr;
@@ -147,11 +180,14 @@ teno_status teno_run_vjp(teno_ctx *c, const void *ckpt_dev, const uint32_t *mask
     const size_t ne = c->nelem, bytes = ne * sizeof(double);
     double *seg = (double *)c->adj_scratch;                 // 3 * ckpt_every states
     double *X = seg + (size_t)3 * ckpt_every * ne;
-    double *mu = X + ne;
-    double *G = mu + ne;
-    double *lam = (double *)lam_io;
+    double *Gy = X + ne;
+    double *muA = Gy + ne, *muB = muA + ne;
+    // the running adjoint of the step input alternates between lam_io and lamB from step to step
+    // (stage 2 reads it as its stencil input while writing the next one; stages 1 and 0 update it in
+    // place, reading only their own cells of it)
+    double *lamv[2] = {(double *)lam_io, muB + ne};
+    int cur = 0;
     const int nseg = (nsteps + ckpt_every - 1) / ckpt_every;
-    const unsigned eblocks = (unsigned)((ne + BLOCK - 1) / BLOCK < 4096 ? (ne + BLOCK - 1) / BLOCK : 4096);
     for (int sgi = nseg - 1; sgi >= 0; --sgi) {
         const int j0 = sgi * ckpt_every;
         const int j1 = j0 + ckpt_every < nsteps ? j0 + ckpt_every : nsteps;
@@ -165,20 +201,29 @@ teno_status teno_run_vjp(teno_ctx *c, const void *ckpt_dev, const uint32_t *mask
             teno_enqueue_step(c, X, 0.0, alpha_dt_dev + (size_t)j * 25, nullptr, nullptr,
                               masks_dev + (size_t)j * 3 * nf, states);
         }
-        // reverse through the steps of the segment
+        // reverse through the steps of the segment: stage 2 (m = lam) starts the next lam buffer and
+        // mu in muA, stage 1 (m = muA) writes muB, stage 0 (m = muB) finishes lam
         for (int j = j1 - 1; j >= j0; --j) {
             const double *s0 = seg + (size_t)3 * (j - j0) * ne;
             const double *ad = alpha_dt_dev + (size_t)j * 25;
             const uint32_t *mj = masks_dev + (size_t)j * 3 * nf;
+            double *lnew = lamv[cur ^ 1];
             for (int k = 2; k >= 0; --k) {
                 const double *Uk = s0 + (size_t)k * ne;
-                const double *in = k == 2 ? lam : mu;       // adjoint of the stage output
-                enqueue_rhs_vjp(c, Uk, mj + (size_t)k * nf, ad + 8 * k, in, G);
-                hipLaunchKernelGGL(rk_adjoint_kernel, dim3(eblocks), dim3(BLOCK), 0, c->stream, k, ne, lam, mu,
-                                   (const double *)G, ad + 24);
+                StageIO io;
+                io.rk = k;
+                io.dt = ad + 24;
+                io.lam_next = lnew;
+                io.lam_step = lnew;
+                io.mu_next = k == 2 ? muA : k == 1 ? muB : nullptr;
+                const double *m = k == 2 ? lamv[cur] : k == 1 ? muA : muB;
+                enqueue_stage_vjp(c, Uk, mj + (size_t)k * nf, ad + 8 * k, m, Gy, io);
             }
+            cur ^= 1;
         }
     }
+    if (cur != 0)
+        HIP_TRY(hipMemcpyAsync(lam_io, lamv[1], bytes, hipMemcpyDeviceToDevice, c->stream));
     return hipGetLastError() == hipSuccess ? TENO_OK : TENO_E_HIP;
 }
 

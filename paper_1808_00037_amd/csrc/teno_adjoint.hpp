@@ -28,14 +28,47 @@ constexpr int ADJ_NSEG = 4;     // segments per block (one per wave)
 struct VjpArgs {
     const double *U;            // state at which the operator is linearised
     const double *lam;          // adjoint of dU/dt
-    double *grad;               // output
+    double *grad;               // output (rk < 0)
     const uint32_t *masks;      // this direction's face mask words
     const double *alpha;        // 8 Lax-Friedrichs constants (device)
     int nx, ny, len, nlines, nseg, bc;
-    int accumulate;             // 0: grad = result, 1: grad += result
+    int accumulate;             // rk < 0: 0 grad = result, 1 grad += result
     int scheme;
     double inv_h, gamma, adv;
+    // rk = 0, 1, 2: the product G = (the other direction's part gy, if any) + this direction's is
+    // not stored; the adjoint of SSP-RK3 stage rk is applied to it in place (rk_stage_adjoint), with
+    // lam (above, the stencil input) the adjoint of the stage output
+    int rk;
+    const double *gy;           // the y-direction part of G (2D), else null
+    double *lam_step;           // rk = 0, 1: the running adjoint of the step's input, updated in place
+    double *lam_next;           // rk = 2: the running adjoint of the step's input, started here
+    double *mu_next;            // rk = 2, 1: the adjoint of the stage input
+    const double *dt;           // the step's dt (device)
 };
+
+// Adjoint of one SSP-RK3 stage (Shu-Osher form) at one element. g = J^T m is the operator's
+// vector-Jacobian product at the stage input, m the adjoint of the stage output, l the running
+// adjoint of the step's input U^n:
+//   k = 2 (U^{n+1} = U^n/3 + 2/3 (U2 + dt L(U2))): m is the adjoint of U^{n+1}; mu <- 2/3 (m + dt g),
+//          l <- m/3
+//   k = 1 (U2 = 3/4 U^n + 1/4 (U1 + dt L(U1))):    l += 3/4 m, mu <- 1/4 (m + dt g)
+//   k = 0 (U1 = U^n + dt L(U^n)):                   l += m + dt g
+struct StageAdj { double l, mu; };
+__device__ __forceinline__ StageAdj rk_stage_adjoint(int k, double m, double l, double g, double dt)
+{
+    StageAdj r;
+    if (k == 2) {
+        r.mu = (2.0 / 3.0) * (m + dt * g);
+        r.l = (1.0 / 3.0) * m;
+    } else if (k == 1) {
+        r.l = l + 0.75 * m;
+        r.mu = 0.25 * (m + dt * g);
+    } else {
+        r.l = l + (m + dt * g);
+        r.mu = 0.0;
+    }
+    return r;
+}
 
 // Flux Jacobian transpose (local order rho, m_n, [m_t], E) applied to g, added to out.
 template <int SYS>
@@ -394,36 +427,37 @@ __global__ void __launch_bounds__(BLOCK) vjp_kernel(VjpArgs a)
                 }
             }
             size_t off = DIR == 0 ? (size_t)line * a.nx + c : (size_t)c * a.nx + line;
+            if (a.rk < 0) {
 #pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                size_t go = (size_t)gvar<SYS, DIR>(v) * ncell + off;
-                a.grad[go] = a.accumulate ? a.grad[go] + tot[v] : tot[v];
+                for (int v = 0; v < NV; ++v) {
+                    size_t go = (size_t)gvar<SYS, DIR>(v) * ncell + off;
+                    a.grad[go] = a.accumulate ? a.grad[go] + tot[v] : tot[v];
+                }
+            } else {
+                // the stage adjoint on the finished product: m is the staged stencil input of this
+                // (owned, so real) cell; every field's operands are read before any store
+                const double dtv = *a.dt;
+                double gv[NV], lv[NV];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    size_t go = (size_t)gvar<SYS, DIR>(v) * ncell + off;
+                    gv[v] = a.gy ? a.gy[go] + tot[v] : tot[v];
+                    lv[v] = a.rk == 2 ? 0.0 : a.lam_step[go];
+                }
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    size_t go = (size_t)gvar<SYS, DIR>(v) * ncell + off;
+                    const double m = R0[SEG_LOAD * (LAM + v) + k + ADJ_HALO];
+                    const StageAdj r = rk_stage_adjoint(a.rk, m, lv[v], gv[v], dtv);
+                    if (a.rk == 2) {
+                        a.lam_next[go] = r.l;
+                        a.mu_next[go] = r.mu;
+                    } else {
+                        a.lam_step[go] = r.l;
+                        if (a.rk == 1) a.mu_next[go] = r.mu;
+                    }
+                }
             }
-        }
-    }
-}
-
-// Adjoint of one SSP-RK3 stage (Shu-Osher form), elementwise. G = J^T mu is the operator's
-// vector-Jacobian product at the stage input, mu the adjoint of the stage output; lam accumulates
-// the adjoint of the step's input U^n:
-//   k = 2 (U^{n+1} = U^n/3 + 2/3 (U2 + dt L(U2))): mu is lam on entry (the adjoint of U^{n+1});
-//          mu <- 2/3 (lam + dt G), lam <- lam/3
-//   k = 1 (U2 = 3/4 U^n + 1/4 (U1 + dt L(U1))):    lam += 3/4 mu, mu <- 1/4 (mu + dt G)
-//   k = 0 (U1 = U^n + dt L(U^n)):                   lam += mu + dt G
-static __global__ void rk_adjoint_kernel(int k, size_t n, double *lam, double *mu, const double *G, const double *dt_ptr)
-{
-    const double dt = *dt_ptr;
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-        if (k == 2) {
-            double l = lam[i];
-            mu[i] = (2.0 / 3.0) * (l + dt * G[i]);
-            lam[i] = (1.0 / 3.0) * l;
-        } else if (k == 1) {
-            double m = mu[i];
-            lam[i] += 0.75 * m;
-            mu[i] = 0.25 * (m + dt * G[i]);
-        } else {
-            lam[i] += mu[i] + dt * G[i];
         }
     }
 }

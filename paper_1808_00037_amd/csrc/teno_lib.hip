@@ -497,7 +497,7 @@ size_t teno_workspace_bytes(const teno_grid *grid, const teno_opts *opts, int32_
     teno_fill_derived(&c);
     const size_t state = c.nelem * c.esize;
     size_t bytes = sizeof(Ctrl) + 2 * state + (grid->sys == TENO_EULER2D ? state : 0);
-    if (ckpt_every > 0) bytes += ((size_t)3 * (size_t)ckpt_every + 3) * c.nelem * sizeof(double);
+    if (ckpt_every > 0) bytes += ((size_t)3 * (size_t)ckpt_every + 5) * c.nelem * sizeof(double);
     return bytes;
 }
 

@@ -145,7 +145,7 @@ def test_workspace_bytes(T):
     state = 4 * 4096 * 4096 * 8
     ctrl = ws(g2) - 3 * state                       # control block: the rest
     assert 0 < ctrl < 1 << 20
-    assert ws(g2, 20) - ws(g2) == (3 * 20 + 3) * state
+    assert ws(g2, 20) - ws(g2) == (3 * 20 + 5) * state
     g1 = _grid(T, sys=T.EULER1D, nx=4096, ny=1)
     assert ws(g1) == ctrl + 2 * 3 * 4096 * 8        # no y-part for one-dimensional systems
     g32 = _grid(T, dtype=T.F32)
