@@ -237,7 +237,9 @@ def batched_speedup(seed=3, nsteps=20):
 
 def adjoint_cost(n=1024, nsteps=400, ckpt=20, seed=21):
     """Frozen-selection adjoint of 2D Euler n x n, nsteps steps, checkpoints every ckpt steps:
-    backward (segment recomputation + reverse sweep) time over the plain forward run time."""
+    backward (segment recomputation + reverse sweep) time over the plain forward run time. Beside it,
+    the same gradient from a recording that keeps every stage input in HBM (no recomputation), its
+    footprint and whether it equals the checkpointed gradient bit for bit."""
     import torch
     from paper_1808_00037_amd import teno as T
     from paper_1808_00037_amd import workloads as W
@@ -268,6 +270,7 @@ def adjoint_cost(n=1024, nsteps=400, ckpt=20, seed=21):
     J = torch.sqrt(torch.sum((U[0] - target) ** 2) * area)
     lam = torch.zeros_like(U)
     lam[0] = (U[0] - target) * area / J
+    lam_T = lam.clone()
     t_bwd = timed(lambda: sv.run_vjp(rec, lam))
     sv.poll()
     # central differences of the frozen map in a few seeded directions (the full 32-direction check
@@ -298,10 +301,27 @@ def adjoint_cost(n=1024, nsteps=400, ckpt=20, seed=21):
     sv.poll()
     an = float(torch.sum(lam * d))
     fd_unfrozen = float((Js[0] - Js[1]) / (2 * h))
-    return {"n": n, "steps": nsteps, "ckpt_every": ckpt, "ms_forward": t_fwd, "ms_record": t_rec,
-            "ms_backward": t_bwd, "bwd_over_fwd": t_bwd / t_fwd, "fwd_plus_bwd_over_fwd": (t_fwd + t_bwd) / t_fwd,
-            "fd_rel_err_2dirs": worst, "unfrozen_fd_rel_err": abs(fd_unfrozen - an) / abs(an),
-            "unfrozen_mask_flips": flips, "mask_words_per_run": int(rec["masks"].numel())}
+    out = {"n": n, "steps": nsteps, "ckpt_every": ckpt, "ms_forward": t_fwd, "ms_record": t_rec,
+           "ms_backward": t_bwd, "bwd_over_fwd": t_bwd / t_fwd, "fwd_plus_bwd_over_fwd": (t_fwd + t_bwd) / t_fwd,
+           "fd_rel_err_2dirs": worst, "unfrozen_fd_rel_err": abs(fd_unfrozen - an) / abs(an),
+           "unfrozen_mask_flips": flips, "mask_words_per_run": int(rec["masks"].numel())}
+    # every stage input kept (3 states per step): the backward pass recomputes nothing
+    masks_bytes = rec["masks"].numel() * 4
+    del rec
+    box.pop("rec", None)
+    torch.cuda.empty_cache()
+    U = U0.clone()
+    t_rec_s = timed(lambda: box.__setitem__("rs", sv.run_record(U, nsteps, T.CKPT_STAGES)))
+    lam_s = lam_T.clone()
+    t_bwd_s = timed(lambda: sv.run_vjp(box["rs"], lam_s))
+    sv.poll()
+    out.update({"ms_record_stored_stages": t_rec_s, "ms_backward_stored_stages": t_bwd_s,
+                "bwd_over_fwd_stored_stages": t_bwd_s / t_fwd,
+                "stored_stages_GB": (box["rs"]["ckpt"].numel() * 8 + masks_bytes) / 1e9,
+                "stored_stages_gradient_bitwise_equal": bool(torch.equal(lam_s, lam))})
+    del box["rs"]
+    torch.cuda.empty_cache()
+    return out
 
 
 def scheme_cost(n=4096, steps=10, seed=1):

@@ -96,8 +96,10 @@ teno_status teno_probe_fp64_fma(void *stream, int32_t iters, double *tflops);
 /* Device memory, in bytes, that a context for (grid, opts) allocates by itself at most: the control
  * block (at teno_create), the SSP-RK3 stage scratch (two states, plus the y-part of dU/dt for 2D
  * Euler; at the first step), and, when ckpt_every > 0, the scratch of a reverse sweep
- * teno_run_vjp(.., ckpt_every, ..) ((3 ckpt_every + 5) double states). Caller-owned buffers
- * (states, masks, checkpoints) are not included. Returns 0 for an invalid grid or opts. */
+ * teno_run_vjp(.., ckpt_every, ..) ((3 ckpt_every + 5) double states; 4 states for
+ * ckpt_every = TENO_CKPT_STAGES). Caller-owned buffers (states, masks, checkpoints) are not
+ * included. Returns 0 for an invalid grid or opts, or a negative ckpt_every other than
+ * TENO_CKPT_STAGES. */
 size_t teno_workspace_bytes(const teno_grid *grid, const teno_opts *opts, int32_t ckpt_every);
 
 /* Create a context for one problem on the current HIP device; `stream` is a hipStream_t (NULL =
@@ -219,6 +221,11 @@ teno_status teno_read_timing(teno_ctx *ctx, double *ms, int32_t *count);
 teno_status teno_rhs_vjp(teno_ctx *ctx, const void *U, const uint32_t *masks, const double *alpha_dev,
                          const void *lam, void *grad);
 
+/* Value of ckpt_every for teno_run_record / teno_run_vjp that stores every stage input of every
+ * step (3 nsteps states in ckpt_dev: for step j, U^n, U1, U2 at states 3j, 3j+1, 3j+2), so that the
+ * reverse sweep recomputes nothing; memory for speed (2D Euler 1024^2, 400 steps: 40 GB). */
+#define TENO_CKPT_STAGES (-1)
+
 /* Forward run of nsteps steps that records what the adjoint needs: ckpt_dev holds
  * ceil(nsteps/ckpt_every) states (the state before steps 0, ckpt_every, 2*ckpt_every, ...),
  * masks_dev (nullable) nsteps*3*teno_nfaces() mask words, alpha_dt_dev nsteps*(3*8+1) doubles
@@ -232,8 +239,10 @@ teno_status teno_run_replay(teno_ctx *ctx, void *U, int32_t nsteps, const uint32
 
 /* Reverse sweep: given lam = dJ/dU(T) in lam_io, overwrite it with dJ/dU(0). Recomputes each
  * checkpoint segment forward (frozen) and applies the adjoint of every RK stage in reverse.
- * Needs masks_dev (recorded). Scratch: 3*ckpt_every+5 double states, allocated on first use
- * (the stage states of one segment, the running state, the y part of J^T mu, two mu and one lam). */
+ * With ckpt_every = TENO_CKPT_STAGES (a recording that stored every stage input) nothing is
+ * recomputed. Needs masks_dev (recorded). Scratch: 3*ckpt_every+5 double states (4 with
+ * TENO_CKPT_STAGES), allocated on first use (the stage states of one segment and the running
+ * state, then the y part of J^T mu, two mu and one lam). */
 teno_status teno_run_vjp(teno_ctx *ctx, const void *ckpt_dev, const uint32_t *masks_dev,
                          const double *alpha_dt_dev, int32_t nsteps, int32_t ckpt_every, void *lam_io);
 

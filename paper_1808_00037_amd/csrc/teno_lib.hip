@@ -490,7 +490,7 @@ teno_status teno_destroy(teno_ctx *c)
 
 size_t teno_workspace_bytes(const teno_grid *grid, const teno_opts *opts, int32_t ckpt_every)
 {
-    if (!teno_validate(grid, opts) || ckpt_every < 0) return 0;
+    if (!teno_validate(grid, opts) || (ckpt_every < 0 && ckpt_every != TENO_CKPT_STAGES)) return 0;
     teno_ctx c;
     c.grid = *grid;
     c.opts = *opts;
@@ -498,6 +498,7 @@ size_t teno_workspace_bytes(const teno_grid *grid, const teno_opts *opts, int32_
     const size_t state = c.nelem * c.esize;
     size_t bytes = sizeof(Ctrl) + 2 * state + (grid->sys == TENO_EULER2D ? state : 0);
     if (ckpt_every > 0) bytes += ((size_t)3 * (size_t)ckpt_every + 5) * c.nelem * sizeof(double);
+    if (ckpt_every == TENO_CKPT_STAGES) bytes += (size_t)4 * c.nelem * sizeof(double);
     return bytes;
 }
 

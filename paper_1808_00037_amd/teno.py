@@ -25,6 +25,7 @@ STATUS = {0: "ok", -1: "invalid argument", -2: "unsupported", -3: "HIP runtime e
           -4: "non-finite value", -5: "non-physical state", -6: "invalid context state",
           -7: "problem exceeds the fixed scratch of the no-allocation entry point"}
 NOALLOC_SCRATCH_BYTES = 16 << 20
+CKPT_STAGES = -1          # ckpt_every that stores every stage input (TENO_CKPT_STAGES)
 
 
 class TenoError(RuntimeError):
@@ -335,9 +336,13 @@ class Solver:
         return out
 
     def run_record(self, U, nsteps, ckpt_every, dt=0.0, record_masks=True):
-        """Advance U in place; returns the recording (checkpoints, masks, alpha/dt)."""
+        """Advance U in place; returns the recording (checkpoints, masks, alpha/dt). ckpt_every =
+        CKPT_STAGES keeps every stage input (3 nsteps states) so that the backward pass recomputes
+        nothing."""
         self._sync_stream()
-        nck = nsteps // ckpt_every + 1
+        if ckpt_every != CKPT_STAGES and ckpt_every < 1:
+            raise ValueError("ckpt_every must be >= 1 or CKPT_STAGES")
+        nck = max(3 * nsteps, 1) if ckpt_every == CKPT_STAGES else nsteps // ckpt_every + 1
         ckpt = torch.empty((nck,) + self.shape, dtype=self.dtype, device="cuda")
         masks = torch.empty((nsteps, 3, self.nfaces), dtype=torch.int32, device="cuda") if record_masks else None
         ad = torch.empty((nsteps, 25), dtype=torch.float64, device="cuda")
@@ -362,7 +367,8 @@ class Solver:
         n, ck = int(rec["nsteps"]), int(rec["ckpt_every"])
         if rec["masks"] is None:
             raise ValueError("the backward pass needs a recording with masks")
-        _buf(rec["ckpt"], (self.dtype,), -(-n // ck) * self.nvar * self.nx * self.ny, "checkpoints")
+        nck = 3 * n if ck == CKPT_STAGES else -(-n // ck)
+        _buf(rec["ckpt"], (self.dtype,), nck * self.nvar * self.nx * self.ny, "checkpoints")
         _buf(rec["masks"], _WORD_TYPES, n * 3 * self.nfaces, "recorded masks")
         _buf(rec["alpha_dt"], (torch.float64,), n * 25, "recorded alpha/dt")
         _check(lib().teno_run_vjp(self._h, _ptr(rec["ckpt"]), _ptr(rec["masks"]), _ptr(rec["alpha_dt"]),
@@ -391,7 +397,8 @@ class TenoRHS(torch.autograd.Function):
 
 class TenoTrajectory(torch.autograd.Function):
     """U(T) after nsteps SSP-RK3 steps from U0, differentiable through the frozen-selection adjoint
-    with checkpoints every ckpt_every steps (the backward pass recomputes one segment at a time)."""
+    with checkpoints every ckpt_every steps (the backward pass recomputes one segment at a time), or
+    with every stage input kept (ckpt_every = CKPT_STAGES: nothing recomputed)."""
 
     @staticmethod
     def forward(ctx, U0, solver, nsteps, ckpt_every, dt=0.0):

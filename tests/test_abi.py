@@ -151,9 +151,20 @@ def test_workspace_bytes(T):
     g32 = _grid(T, dtype=T.F32)
     assert ws(g32) == ctrl + 3 * 4 * 64 * 32 * 4
     assert ws(_grid(T, nx=0)) == 0
-    assert ws(g2, -1) == 0
+    assert ws(g2, T.CKPT_STAGES) - ws(g2) == 4 * state     # every stage input stored: no segment scratch
+    assert ws(g2, -2) == 0
     bad = T.Opts()
     T.lib().teno_default_opts(ctypes.byref(bad))
     bad.q = 0
     assert L.teno_workspace_bytes(ctypes.byref(g2), ctypes.byref(bad), 0) == 0
     assert T.workspace_bytes(T.EULER2D, 4096, 4096, ckpt_every=20) == ws(g2, 20)
+
+
+def test_binding_constants_match_the_header():
+    text = open(HEADER).read()
+    m = re.search(r"#define\s+TENO_CKPT_STAGES\s+\((-?\d+)\)", text)
+    assert m and int(m.group(1)) == -1
+    from paper_1808_00037_amd import teno
+    assert teno.CKPT_STAGES == int(m.group(1))
+    m = re.search(r"#define\s+TENO_NOALLOC_SCRATCH_BYTES\s+\((\d+)u << (\d+)\)", text)
+    assert m and teno.NOALLOC_SCRATCH_BYTES == int(m.group(1)) << int(m.group(2))

@@ -192,6 +192,35 @@ def test_trajectory_gradient_matches_central_differences():
     sv.poll()
 
 
+@pytest.mark.parametrize("sys,nsteps", [("e2", 7), ("e2", 8), ("e1", 9)])
+def test_stored_stages_equal_checkpointed(sys, nsteps):
+    """A recording that keeps every stage input (CKPT_STAGES) against checkpoints every 3 steps:
+    the same forward state and masks, and the same gradient bit for bit (the frozen replay of a
+    checkpointed segment reproduces the stored stage inputs exactly, and the reverse steps are the
+    same launches). Odd and even step counts cover both buffers the running adjoint ends in."""
+    if sys == "e2":
+        pr = W.euler2d(31, n=72, ny=60)
+    else:
+        pr = W.euler1d(32, n=150)
+    print(f"[case] stored stages {sys} {nsteps} steps", flush=True)
+    sv = solver_for(pr)
+    U0 = torch.from_numpy(pr.U0.copy()).cuda()
+    Ua, Ub = U0.clone(), U0.clone()
+    ra = sv.run_record(Ua, nsteps, 3)
+    rb = sv.run_record(Ub, nsteps, T.CKPT_STAGES)
+    sv.poll()
+    assert torch.equal(Ua, Ub)
+    assert torch.equal(ra["masks"], rb["masks"]) and torch.equal(ra["alpha_dt"], rb["alpha_dt"])
+    assert rb["ckpt"].shape[0] == 3 * nsteps and torch.equal(rb["ckpt"][0], U0)
+    lam0 = torch.from_numpy(W.random_directions(33, pr.U0, 1)[0]).cuda()
+    la, lb = lam0.clone(), lam0.clone()
+    sv.run_vjp(ra, la)
+    sv.run_vjp(rb, lb)
+    sv.poll()
+    assert torch.equal(la, lb)
+    assert float(la.abs().max()) > 0
+
+
 def test_autograd_functions():
     pr = W.euler2d(12, n=40, ny=30)
     sv = solver_for(pr)
