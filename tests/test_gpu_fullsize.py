@@ -89,6 +89,23 @@ def test_operator_matches_the_oracle_on_every_face(problem):
     _face_check(pr, solver_for(pr), pr.U0, tag="teno7x")
 
 
+def test_operator_matches_the_oracle_after_gpu_steps(problem):
+    """State handoff: the GPU advances the benchmark state 40 SSP-RK3 steps (graph replay); both
+    implementations then evaluate the operator on that state, whose shocks and contact layers have
+    formed and steepened, so far more faces take the cut-off and selection path than at t = 0. Every
+    face, the census and every cell's derivative, as at t = 0."""
+    pr = problem
+    print("[case] full-size operator after 40 GPU steps", flush=True)
+    sv = solver_for(pr)
+    U = torch.from_numpy(pr.U0).cuda()
+    sv.run(U, 40, graph=True)
+    sv.poll()
+    U_np = U.cpu().numpy()
+    del U
+    rep = _face_check(pr, sv, U_np, tag="teno7x after 40 steps")
+    assert rep["faces"] == 2 * N * (N + 1)
+
+
 def test_step_matches_the_oracle_everywhere(problem):
     """One SSP-RK3 step with the benchmark's kernels (graph replay, whole-line x tiles, fused stage
     epilogue) against the oracle's step, cell by cell; the recorded selection of each stage against
