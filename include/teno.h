@@ -229,7 +229,8 @@ teno_status teno_rhs_vjp(teno_ctx *ctx, const void *U, const uint32_t *masks, co
 /* Forward run of nsteps steps that records what the adjoint needs: ckpt_dev holds
  * ceil(nsteps/ckpt_every) states (the state before steps 0, ckpt_every, 2*ckpt_every, ...),
  * masks_dev (nullable) nsteps*3*teno_nfaces() mask words, alpha_dt_dev nsteps*(3*8+1) doubles
- * (per step: the three stages' eight constants, then dt). U is advanced in place. */
+ * (per step: the three stages' eight constants, then dt). U is advanced in place. ckpt_every must be
+ * >= 1 or TENO_CKPT_STAGES (ckpt_dev then holds 3*nsteps states); otherwise TENO_E_ARG. */
 teno_status teno_run_record(teno_ctx *ctx, void *U, int32_t nsteps, double dt_fixed, int32_t ckpt_every,
                             void *ckpt_dev, uint32_t *masks_dev, double *alpha_dt_dev);
 
