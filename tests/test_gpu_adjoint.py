@@ -229,6 +229,12 @@ def test_autograd_functions():
     loss = (Ut[0] ** 2).sum()
     loss.backward()
     assert U0.grad is not None and torch.isfinite(U0.grad).all()
+    # every stage input kept: the same gradient bit for bit
+    U0s = torch.from_numpy(pr.U0.copy()).cuda().requires_grad_(True)
+    Uts = T.trajectory(U0s, sv, 4, ckpt_every=T.CKPT_STAGES)
+    assert torch.equal(Uts.detach(), Ut.detach())
+    (Uts[0] ** 2).sum().backward()
+    assert torch.equal(U0s.grad, U0.grad)
     U1 = torch.from_numpy(pr.U0.copy()).cuda().requires_grad_(True)
     r = T.rhs(U1, sv)
     w = torch.randn_like(r)
