@@ -1,8 +1,9 @@
 """Batched runs of many uneven Euler instances (1D and 2D mixed) through the C ABI.
 
 The graph-captured form (mode 0: static work-list launches over all instances, autotuned tile
-shapes) and the one-launch-per-instance form (mode 1) must give bitwise identical states, each equal bitwise to the instance run alone with
-the single-problem solver, and the oracle agrees with an instance after a few steps.
+shapes) and the one-launch-per-instance form (mode 1) must give bitwise identical states, each equal
+bitwise to the instance run alone with the single-problem solver, and the oracle agrees with an
+instance after a few steps.
 """
 import numpy as np
 import pytest
