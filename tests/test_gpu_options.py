@@ -70,6 +70,31 @@ def test_componentwise_adjoint_is_refused():
     sv.poll()
 
 
+def test_recording_rejects_invalid_checkpoint_intervals():
+    """ckpt_every must be >= 1 or CKPT_STAGES: the C ABI refuses anything else before enqueueing work
+    (the state is left untouched)."""
+    import ctypes
+    pr = W.euler2d(65, n=32, ny=24)
+    sv = solver_for(pr)
+    U = torch.from_numpy(pr.U0.copy()).cuda()
+    U_before = U.clone()
+    ck = torch.empty((3,) + tuple(U.shape), dtype=U.dtype, device="cuda")
+    ad = torch.empty((1, 25), dtype=torch.float64, device="cuda")
+    L = T.lib()
+    for bad in (0, -2, -100):
+        code = L.teno_run_record(sv._h, ctypes.c_void_p(U.data_ptr()), 1, 0.0, bad, ctypes.c_void_p(ck.data_ptr()),
+                                 None, ctypes.c_void_p(ad.data_ptr()))
+        assert code == -1, (bad, code)
+        code = L.teno_run_vjp(sv._h, ctypes.c_void_p(ck.data_ptr()), ctypes.c_void_p(ad.data_ptr()),
+                              ctypes.c_void_p(ad.data_ptr()), 1, bad, ctypes.c_void_p(U.data_ptr()))
+        assert code == -1, (bad, code)
+    torch.cuda.synchronize()
+    assert torch.equal(U, U_before)
+    with pytest.raises(ValueError):
+        sv.run_record(U, 1, 0)
+    sv.poll()
+
+
 def _oracle_failing_step(pr, nmax):
     """Index of the first step of the oracle's trajectory that produces a non-physical state (in any
     of its stages), and the oracle's state before it."""
