@@ -758,6 +758,23 @@ __device__ __forceinline__ bool cell_primitive_speeds(const T *u, T gamma, T gm1
     }
 }
 
+// The physicality test of cell_primitive_speeds alone (rho > 0, p > 0, finite energy; scalar systems:
+// a finite value), the same arithmetic.
+template <typename T, int SYS>
+__device__ __forceinline__ bool cell_physical(const T *u, T gm1)
+{
+    if constexpr (SYS == ADV1D || SYS == BURGERS1D) {
+        return isfinite(u[0]);
+    } else {
+        constexpr int NV = Sys<SYS>::NV;
+        T rho = u[0], mx = u[1], my = NV == 4 ? u[2] : T(0), E = u[NV - 1];
+        T ir = recip(rho);
+        T vx = mx * ir, vy = my * ir;
+        T p = gm1 * (E - T(0.5) * rho * (vx * vx + vy * vy));
+        return rho > T(0) && p > T(0) && isfinite(E);
+    }
+}
+
 // The words of the wave-speed record a system with NV conserved variables produces (the second
 // acoustic-free x/y field repeats the first), and their indices packed 4 bits per used slot.
 template <int NV> struct SpeedWords {
@@ -1446,14 +1463,18 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs<T> &a, int tile, T *r
                         unew[gvar<SYS, DIR>(v)] = un;
                     }
                 }
-                if constexpr (MODE == MODE_STAGE) {
+                if constexpr (MODE == MODE_STAGE && FROZEN) {
+                    // a replay takes its constants and dt from the recording: no maxima, only the
+                    // produced state's check
+                    if (!cell_physical<T, SYS>(unew, a.gm1)) bad |= ERR_NONPHYSICAL;
+                } else if constexpr (MODE == MODE_STAGE) {
                     if (!cell_primitive_speeds<T, SYS>(unew, a.gamma, a.gm1, a.adv, sx, sy, sc)) {
                         bad |= ERR_NONPHYSICAL;       // reported; keep the maxima finite
                         sx = sy = sc = 0.0;
                     }
                 }
             }
-            if constexpr (MODE == MODE_STAGE) {
+            if constexpr (MODE == MODE_STAGE && !FROZEN) {
                 // this segment's maxima into the wave's LDS slots (the wave owns them: no race)
                 constexpr int NU = SpeedWords<NV>::count();
                 constexpr int WSTRIDE = WAVE + 1;          // per word, padded against bank conflicts
